@@ -1,0 +1,51 @@
+"""Weak pins of the whole oracle against the errors printed in Table 6 (Sec. 4.6).
+
+The advective Brusselator experiment has deterministic initial data, so the
+oracle can rerun it: 64^3 grid, T = 1, errors of ETD2RKds and Lawson2b against
+a reference run with many more steps.  Matching the printed errors pins the
+grid convention, the boundary rows, the matrix functions, the reaction terms
+and the structure of both schemes at once.  The paper does not state the
+reference step count; here the reference is a Richardson extrapolation of
+two fine runs, so that its own error is third order.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth as S
+
+TAB = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))
+
+
+def _run(steps, scheme="etd2rkds"):
+    w = S.paper_brusselator_3d(64, steps=steps)
+    p = O.problem_from_workload(w)
+    U0, V0 = S.initial_state(w)
+    return O.solve(U0, V0, p, steps, scheme)
+
+
+def _reference(s1, s2):
+    U1, V1 = _run(s1)
+    U2, V2 = _run(s2)
+    return (4 * U2 - U1) / 3, (4 * V2 - V1) / 3
+
+
+def test_table6_etd2rkds_first_row():
+    row = TAB["table6_brusselator3d"]["etd2rkds"]
+    Ur, Vr = _reference(200, 400)
+    err = O.relative_error(*_run(50), Ur, Vr)
+    assert err == pytest.approx(row["error"][0], rel=0.01)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("scheme", ["etd2rkds", "lawson2b"])
+def test_table6_all_rows(scheme):
+    row = TAB["table6_brusselator3d"][scheme]
+    Ur, Vr = _reference(800, 1600)
+    errs = [O.relative_error(*_run(s, scheme), Ur, Vr) for s in row["steps"]]
+    for got, want in zip(errs, row["error"]):
+        assert got == pytest.approx(want, rel=0.01)
+    assert np.allclose(np.round(O.observed_order(row["steps"], errs), 2), row["order"], atol=0.02)
