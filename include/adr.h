@@ -1,0 +1,196 @@
+/*
+ * adr.h -- C ABI of the MI355X (gfx950) ETD2RKds library, libadr.so.
+ *
+ * Solves two-component advection-diffusion-reaction systems on tensor-product
+ * grids, in the form of Caliari & Cassini, "A second order directional split
+ * exponential integrator for systems of advection-diffusion-reaction
+ * equations" (arXiv 2307.10684):
+ *
+ *   U' = sum_mu U x_mu A_mu^u + G^u(U, V),   V' = sum_mu V x_mu A_mu^v + G^v(U, V)
+ *
+ * (Sec. 1 eqs. (1)-(3), Sec. 2 eq. (6)), time-stepped by ETD2RKds (Sec. 3,
+ * eq. (11)) or Lawson2b (Sec. 2, eq. (7)) with a constant step tau whose small
+ * matrix functions are computed once (Sec. 4, opening paragraphs).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Status: every function returns an int, ADR_OK (0) on success or a negative
+ *   adr_status.  Arguments are validated before any work is enqueued; on
+ *   ADR_EINVAL nothing has been written.  No C++ exception crosses the ABI.
+ * - Layout: a grid tensor of order d with sizes n[0..d-1] is a dense array of
+ *   N = n[0]*...*n[d-1] elements with n[0] (direction mu = 1) fastest, i.e. the
+ *   vec ordering of Sec. 2.  Small n x n matrices are column-major.
+ * - Memory: every pointer argument is owned by the caller.  "device" pointers
+ *   are HIP device allocations on the current device; "host" pointers are
+ *   ordinary CPU memory.  The library never frees caller memory.
+ * - Streams: `stream` is a hipStream_t passed as void* (NULL = the legacy
+ *   default stream).  Device work is enqueued asynchronously on it; unless a
+ *   function says otherwise it does not synchronise.
+ * - Aliasing: outputs must not alias inputs unless a function says so.
+ */
+#ifndef ADR_H
+#define ADR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum adr_status {
+  ADR_OK = 0,
+  ADR_EINVAL = -1,     /* invalid argument (null pointer, size, step, enum) */
+  ADR_ENOMEM = -2,     /* workspace too small or a temporary allocation failed */
+  ADR_EDEVICE = -3,    /* a HIP call or kernel launch failed */
+  ADR_ENOTSUP = -4,    /* valid but unsupported combination */
+  ADR_ENONFINITE = -5  /* a non-finite value was found where none may be */
+};
+
+enum adr_bc { ADR_BC_NEUMANN = 0 };                 /* homogeneous Neumann, Sec. 1 */
+enum adr_scheme { ADR_ETD2RKDS = 0,                 /* Sec. 3, eq. (11) */
+                  ADR_LAWSON2B = 1 };               /* Sec. 2, eq. (7)  */
+enum adr_precision { ADR_F64 = 0,                   /* all arithmetic in FP64 */
+                     ADR_F32 = 1,                   /* mode products in FP32 */
+                     ADR_BF16X3 = 2 };              /* mode products in 3-term split BF16 */
+/* Reaction models G^u, G^v and the order of adr_problem.params:
+ *   ADR_SCHNAKENBERG (gamma, a, b):   gamma(a - u + u^2 v),  gamma(b - u^2 v)    Sec. 4.1 eq. (12)
+ *   ADR_FHN          (rho, eps, a1, a0): rho(u - u^3 - v),  rho eps(u - a1 v - a0)  Secs. 4.2-4.3
+ *   ADR_BRUSSELATOR  (A, B):          A - (B+1)u + u^2 v,    B u - u^2 v        Sec. 4.6 eq. (17)
+ *   ADR_ZERO         ():              0, 0  (pure advection-diffusion)            */
+enum adr_model { ADR_SCHNAKENBERG = 0, ADR_FHN = 1, ADR_BRUSSELATOR = 2, ADR_ZERO = 3 };
+
+#define ADR_MAX_DIM 3
+
+/* Human-readable text of a status code (static storage, never NULL). */
+const char* adr_strerror(int status);
+
+/* Library ABI version (major*10000 + minor*100 + patch). */
+int adr_version(void);
+
+/*
+ * adr_build_1d_ops -- the 1D operator A = diff * d^2/dx^2 - vel * d/dx on [a, b]
+ * by second-order centred finite differences with homogeneous Neumann
+ * conditions embedded in the matrix (Sec. 4, opening paragraphs).  Grid nodes
+ * are node-centred, x_i = a + i h, h = (b - a)/(n - 1), and the boundary rows
+ * use the ghost values u_{-1} = u_1, u_n = u_{n-2}: diffusion rows
+ * diff*(-2, 2)/h^2 and diff*(2, -2)/h^2, advection rows 0.
+ *   n        grid points, n >= 3
+ *   bc       ADR_BC_NEUMANN (the only condition the paper uses)
+ *   A        host, n*n doubles, column-major; may be NULL
+ *   band     host, 3*n doubles: band[i] = A[i,i-1] (band[0] = 0),
+ *            band[n+i] = A[i,i], band[2n+i] = A[i,i+1] (band[3n-1] = 0); may be NULL
+ * Pure host computation; errors: ADR_EINVAL (n < 3, b <= a, non-finite input,
+ * unknown bc, both outputs NULL).
+ */
+int adr_build_1d_ops(int n, double a, double b, double diff, double vel, int bc,
+                     double* A, double* band);
+
+/*
+ * adr_precompute_phi -- E = e^{tau A}, P1 = phi_1(tau A), P2 = phi_2(tau A) of
+ * one n x n matrix, with phi_l(X) = int_0^1 theta^{l-1}/(l-1)! e^{(1-theta)X} dtheta
+ * (Sec. 2, eq. (9)).  Computed on the device in FP64 by a degree-18 Taylor
+ * polynomial of the scaled matrix tau*A/2^s followed by s steps of the
+ * modified squaring of Skaflestad & Wright (cited in Sec. 4).
+ *   A_dev            device, n*n doubles, column-major
+ *   E_dev, P1_dev, P2_dev  device, n*n doubles each; any may be NULL (not computed)
+ *   n                1 <= n <= 4096
+ * Allocates a temporary device workspace of 10*n*n doubles and synchronises
+ * `stream` once (to read back ||tau A||_1 and pick s).  Errors: ADR_EINVAL,
+ * ADR_ENOMEM, ADR_EDEVICE, ADR_ENONFINITE (tau*A has a non-finite entry).
+ */
+int adr_precompute_phi(int n, const double* A_dev, double tau, double* E_dev,
+                       double* P1_dev, double* P2_dev, void* stream);
+
+/*
+ * One problem instance: grid, model, scheme, and the device-resident small
+ * matrices.  The tensors U, V are passed separately to adr_step/adr_solve.
+ */
+typedef struct adr_problem {
+  int32_t d;                   /* space dimension, 1..3 */
+  int32_t n[ADR_MAX_DIM];      /* grid sizes, n[0] fastest; entries >= d ignored; each 3..4096 */
+  int32_t model;               /* enum adr_model */
+  int32_t scheme;              /* enum adr_scheme */
+  int32_t precision;           /* enum adr_precision */
+  int32_t flags;               /* reserved, must be 0 */
+  double params[8];            /* model constants, order as in enum adr_model */
+  double tau;                  /* time step, > 0 (used for the stage scalings) */
+  /* phi[c][j][mu]: device n[mu] x n[mu] FP64 column-major matrices of
+   * component c (0 = u, 1 = v), j = 0: e^{tau A}, 1: phi_1(tau A), 2: phi_2(tau A).
+   * ETD2RKds needs j = 1, 2; Lawson2b needs j = 0. */
+  const double* phi[2][3][ADR_MAX_DIM];
+  /* band[c][mu]: device 3*n[mu] doubles, the tridiagonal of A_mu^c in the
+   * layout of adr_build_1d_ops.  If NULL, dense[c][mu] is used instead. */
+  const double* band[2][ADR_MAX_DIM];
+  /* dense[c][mu]: device n[mu] x n[mu] FP64 A_mu^c (only read when band is NULL
+   * and the scheme is ETD2RKds; any sparsity pattern is allowed, Sec. 1). */
+  const double* dense[2][ADR_MAX_DIM];
+} adr_problem;
+
+/* Bytes of device workspace adr_step/adr_solve need for this problem (0 on invalid input). */
+size_t adr_workspace_bytes(const adr_problem* p);
+
+/*
+ * adr_step -- advance (U, V) by one step of p->scheme in place.
+ *   U, V   device, N doubles each (FP64 state in every precision mode)
+ *   work   device, at least adr_workspace_bytes(p) bytes, 256-byte aligned
+ * Enqueues 2*d mode-product launches and 2 stage launches (ETD2RKds) on
+ * `stream`; no synchronisation.  Errors: ADR_EINVAL, ADR_ENOMEM (work too
+ * small), ADR_ENOTSUP, ADR_EDEVICE.
+ */
+int adr_step(const adr_problem* p, double* U, double* V, void* work, size_t work_bytes,
+             void* stream);
+
+/* adr_solve -- nsteps >= 0 calls of adr_step with one validation (same arguments). */
+int adr_solve(const adr_problem* p, double* U, double* V, int nsteps, void* work,
+              size_t work_bytes, void* stream);
+
+/*
+ * adr_mode_product -- out = alpha * (W x_mu M) + beta * Y, the mu-mode product
+ * of Sec. 2 ((W x_mu M)[.., i, ..] = sum_k M[i,k] W[.., k, ..]) with an
+ * optional scaled addend, in FP64.
+ *   d, n      tensor order (1..3) and sizes (n[0] fastest), each n >= 1
+ *   mu        0-based direction (paper's mu - 1), 0 <= mu < d
+ *   M         device n[mu] x n[mu] column-major
+ *   W, out    device N doubles; out must not alias W
+ *   Y         device N doubles or NULL (then beta is ignored); Y may alias out
+ * Errors: ADR_EINVAL, ADR_EDEVICE.
+ */
+int adr_mode_product(int d, const int32_t* n, int mu, const double* M, const double* W,
+                     double* out, double alpha, double beta, const double* Y, void* stream);
+
+/*
+ * adr_tucker -- out = alpha * (W x_1 M[0] x_2 ... x_d M[d-1]) + beta * Y, the
+ * Tucker operator of Sec. 2 eq. (5), applied in the order mu = 1..d.
+ *   M         array of d device matrices (n[mu] x n[mu], column-major)
+ *   work      device, >= adr_tucker_workspace_bytes(d, n) bytes
+ * out may not alias W; Y may alias out.  Errors as adr_mode_product, plus ADR_ENOMEM.
+ */
+size_t adr_tucker_workspace_bytes(int d, const int32_t* n);
+int adr_tucker(int d, const int32_t* n, const double* const* M, const double* W, double* out,
+               double alpha, double beta, const double* Y, void* work, size_t work_bytes,
+               void* stream);
+
+/*
+ * adr_device_copy -- out[i] = in[i] for i < count (doubles), a plain streaming
+ * copy used to calibrate hardware byte counters against known traffic.
+ */
+int adr_device_copy(const double* in, double* out, size_t count, void* stream);
+
+/*
+ * Kernel timing.  adr_timing_enable(capacity) makes later adr_step/adr_solve/
+ * adr_tucker/adr_mode_product calls record a HIP event pair around each of
+ * their kernel launches, on the stream the kernel runs on, for up to
+ * `capacity` launches (capacity 0 disables timing and frees the events).
+ * adr_timing_read synchronises on the recorded events and returns, for the
+ * kernel class `kind` (0 = mode product, 1 = stage kernels, 2 = all), the
+ * number of launches and their summed duration in milliseconds, then clears
+ * the record.  Not thread-safe; intended for benchmarks.
+ */
+int adr_timing_enable(int capacity);
+int adr_timing_read(int kind, int* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADR_H */

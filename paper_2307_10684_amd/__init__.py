@@ -1,0 +1,308 @@
+"""Python binding of libadr.so: the MI355X ETD2RKds hot path.
+
+A thin ctypes layer over the C ABI declared in ``include/adr.h``: every
+function here marshals arguments and calls the entry point of the same name;
+all arithmetic of the method runs in the library's HIP kernels.  PyTorch is
+only used to own device memory and to name the current HIP stream.
+
+``torch`` is imported before the library is loaded so that both use one HIP
+runtime.  If ``libadr.so`` has not been built the import fails loudly; there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # noqa: F401  (load torch's HIP runtime first)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libadr.so")
+
+ADR_OK, ADR_EINVAL, ADR_ENOMEM, ADR_EDEVICE, ADR_ENOTSUP, ADR_ENONFINITE = 0, -1, -2, -3, -4, -5
+ADR_BC_NEUMANN = 0
+ADR_ETD2RKDS, ADR_LAWSON2B = 0, 1
+ADR_F64, ADR_F32, ADR_BF16X3 = 0, 1, 2
+ADR_SCHNAKENBERG, ADR_FHN, ADR_BRUSSELATOR, ADR_ZERO = 0, 1, 2, 3
+
+MODEL_IDS = {"schnakenberg": ADR_SCHNAKENBERG, "fhn": ADR_FHN,
+             "brusselator": ADR_BRUSSELATOR, "zero": ADR_ZERO}
+SCHEME_IDS = {"etd2rkds": ADR_ETD2RKDS, "lawson2b": ADR_LAWSON2B}
+PRECISION_IDS = {"f64": ADR_F64, "f32": ADR_F32, "bf16x3": ADR_BF16X3}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class AdrProblem(ctypes.Structure):
+    """Mirror of ``adr_problem`` in include/adr.h."""
+
+    _fields_ = [
+        ("d", ctypes.c_int32),
+        ("n", ctypes.c_int32 * 3),
+        ("model", ctypes.c_int32),
+        ("scheme", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+        ("params", ctypes.c_double * 8),
+        ("tau", ctypes.c_double),
+        ("phi", ((ctypes.c_void_p * 3) * 3) * 2),
+        ("band", (ctypes.c_void_p * 3) * 2),
+        ("dense", (ctypes.c_void_p * 3) * 2),
+    ]
+
+
+class AdrError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {adr_strerror(status)} ({status})")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2307_10684_amd.build` "
+            "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    c_int, c_double, c_size, c_void = ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
+    sig = {
+        "adr_strerror": (ctypes.c_char_p, [c_int]),
+        "adr_version": (c_int, []),
+        "adr_build_1d_ops": (c_int, [c_int, c_double, c_double, c_double, c_double, c_int, c_void, c_void]),
+        "adr_precompute_phi": (c_int, [c_int, c_void, c_double, c_void, c_void, c_void, c_void]),
+        "adr_workspace_bytes": (c_size, [ctypes.POINTER(AdrProblem)]),
+        "adr_step": (c_int, [ctypes.POINTER(AdrProblem), c_void, c_void, c_void, c_size, c_void]),
+        "adr_solve": (c_int, [ctypes.POINTER(AdrProblem), c_void, c_void, c_int, c_void, c_size, c_void]),
+        "adr_mode_product": (c_int, [c_int, ctypes.POINTER(ctypes.c_int32), c_int, c_void, c_void, c_void,
+                                     c_double, c_double, c_void, c_void]),
+        "adr_tucker_workspace_bytes": (c_size, [c_int, ctypes.POINTER(ctypes.c_int32)]),
+        "adr_tucker": (c_int, [c_int, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(c_void), c_void, c_void,
+                               c_double, c_double, c_void, c_void, c_size, c_void]),
+        "adr_device_copy": (c_int, [c_void, c_void, c_size, c_void]),
+        "adr_timing_enable": (c_int, [c_int]),
+        "adr_timing_read": (c_int, [c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_double)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = ("adr_strerror", "adr_version", "adr_build_1d_ops", "adr_precompute_phi",
+            "adr_workspace_bytes", "adr_step", "adr_solve", "adr_mode_product",
+            "adr_tucker_workspace_bytes", "adr_tucker", "adr_device_copy",
+            "adr_timing_enable", "adr_timing_read")
+
+
+def _check(status: int, where: str):
+    if status != ADR_OK:
+        raise AdrError(status, where)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dims(n: Sequence[int]):
+    arr = (ctypes.c_int32 * 3)(*(list(n) + [1] * (3 - len(n))))
+    return arr
+
+
+def _f64_cuda(t, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+
+
+# ----------------------------------------------------------------------------- ABI wrappers
+
+def adr_strerror(status: int) -> str:
+    return _lib.adr_strerror(status).decode()
+
+
+def adr_version() -> int:
+    return _lib.adr_version()
+
+
+def adr_build_1d_ops(n: int, a: float, b: float, diff: float, vel: float, bc: int = ADR_BC_NEUMANN):
+    """Host call: returns (A (n x n, numpy, column-major semantics), band (3, n))."""
+    A = np.zeros((n, n), dtype=np.float64, order="F")
+    band = np.zeros(3 * n, dtype=np.float64)
+    _check(_lib.adr_build_1d_ops(n, a, b, diff, vel, bc, A.ctypes.data, band.ctypes.data),
+           "adr_build_1d_ops")
+    return A, band.reshape(3, n)
+
+
+def adr_precompute_phi(A_dev: torch.Tensor, tau: float, E=None, P1=None, P2=None, stream=None,
+                       want=(True, True, True)):
+    """E, phi_1, phi_2 of tau*A on the device.  A_dev is an (n, n) float64 CUDA tensor
+    holding the column-major matrix (i.e. the transpose in torch's row-major view
+    is never taken: pass ``torch.from_numpy(A.ravel(order='F'))``-style data)."""
+    n = int(round(math.sqrt(A_dev.numel())))
+    _f64_cuda(A_dev, "A_dev")
+    outs = []
+    for t, w in zip((E, P1, P2), want):
+        if t is None and w:
+            t = torch.empty(n * n, dtype=torch.float64, device=A_dev.device)
+        outs.append(t)
+    _check(_lib.adr_precompute_phi(n, _ptr(A_dev), float(tau), _ptr(outs[0]), _ptr(outs[1]),
+                                   _ptr(outs[2]), _stream(stream)), "adr_precompute_phi")
+    return tuple(outs)
+
+
+def adr_workspace_bytes(problem: AdrProblem) -> int:
+    return int(_lib.adr_workspace_bytes(ctypes.byref(problem)))
+
+
+def adr_step(problem: AdrProblem, U, V, work, stream=None):
+    _check(_lib.adr_step(ctypes.byref(problem), _ptr(U), _ptr(V), _ptr(work),
+                         work.numel() * work.element_size(), _stream(stream)), "adr_step")
+
+
+def adr_solve(problem: AdrProblem, U, V, nsteps: int, work, stream=None):
+    _check(_lib.adr_solve(ctypes.byref(problem), _ptr(U), _ptr(V), int(nsteps), _ptr(work),
+                          work.numel() * work.element_size(), _stream(stream)), "adr_solve")
+
+
+def adr_mode_product(n: Sequence[int], mu: int, M, W, out, alpha=1.0, beta=0.0, Y=None, stream=None):
+    _check(_lib.adr_mode_product(len(n), _dims(n), mu, _ptr(M), _ptr(W), _ptr(out), float(alpha),
+                                 float(beta), _ptr(Y), _stream(stream)), "adr_mode_product")
+
+
+def adr_tucker_workspace_bytes(n: Sequence[int]) -> int:
+    return int(_lib.adr_tucker_workspace_bytes(len(n), _dims(n)))
+
+
+def adr_tucker(n: Sequence[int], Ms, W, out, alpha=1.0, beta=0.0, Y=None, work=None, stream=None):
+    arr = (ctypes.c_void_p * len(n))(*[_ptr(M) for M in Ms])
+    wb = 0 if work is None else work.numel() * work.element_size()
+    _check(_lib.adr_tucker(len(n), _dims(n), arr, _ptr(W), _ptr(out), float(alpha), float(beta),
+                           _ptr(Y), _ptr(work), wb, _stream(stream)), "adr_tucker")
+
+
+def adr_device_copy(src, dst, count: int, stream=None):
+    _check(_lib.adr_device_copy(_ptr(src), _ptr(dst), int(count), _stream(stream)), "adr_device_copy")
+
+
+def adr_timing_enable(capacity: int):
+    _check(_lib.adr_timing_enable(int(capacity)), "adr_timing_enable")
+
+
+def adr_timing_read(kind: int):
+    launches = ctypes.c_int(0)
+    total = ctypes.c_double(0.0)
+    _check(_lib.adr_timing_read(int(kind), ctypes.byref(launches), ctypes.byref(total)),
+           "adr_timing_read")
+    return launches.value, total.value
+
+
+# ----------------------------------------------------------------------------- problem setup
+
+def to_device_f64(x: np.ndarray, device="cuda") -> torch.Tensor:
+    """Upload a numpy array in its first-index-fastest (Fortran) element order."""
+    flat = np.ascontiguousarray(np.asarray(x, dtype=np.float64).ravel(order="F"))
+    return torch.from_numpy(flat).to(device)
+
+
+def from_device(t: torch.Tensor, shape) -> np.ndarray:
+    return np.asfortranarray(t.detach().cpu().numpy().reshape(tuple(shape), order="F"))
+
+
+class Solver:
+    """Sets up one workload on the device: 1D operators, their matrix functions,
+    the problem record and the workspace; then steps the state in place.
+
+    ``workload`` is any object with the fields of ``synth.Workload`` (n,
+    domain, diff, vel_u, vel_v, model, params, tau).  ``phis`` may supply the
+    small matrices from elsewhere as ``phis[c][j][mu]`` numpy arrays (j = 0 exp,
+    1 phi_1, 2 phi_2); by default they are computed on the device with
+    adr_precompute_phi.
+    """
+
+    def __init__(self, workload, scheme: str = "etd2rkds", precision: str = "f64",
+                 device: str = "cuda", phis=None, use_band: bool = True, stream=None):
+        w = workload
+        self.workload = w
+        self.shape = tuple(int(x) for x in w.n)
+        self.d = len(self.shape)
+        self.N = int(np.prod(self.shape))
+        self.device = device
+        self.stream = stream
+        self.A_host = [[None] * self.d for _ in range(2)]
+        self.keep = []  # device buffers referenced by the problem record
+        p = AdrProblem()
+        p.d = self.d
+        for mu in range(3):
+            p.n[mu] = self.shape[mu] if mu < self.d else 1
+        p.model = MODEL_IDS[w.model]
+        p.scheme = SCHEME_IDS[scheme]
+        p.precision = PRECISION_IDS[precision]
+        p.flags = 0
+        for i, v in enumerate(w.params):
+            p.params[i] = float(v)
+        p.tau = float(w.tau)
+        for c in range(2):
+            vel = w.vel_u if c == 0 else w.vel_v
+            for mu in range(self.d):
+                a, b = w.domain[mu]
+                A, band = adr_build_1d_ops(self.shape[mu], a, b, w.diff[c], vel[mu])
+                self.A_host[c][mu] = A
+                A_dev = to_device_f64(A, device)
+                self.keep.append(A_dev)
+                p.dense[c][mu] = A_dev.data_ptr()
+                if use_band:
+                    band_dev = torch.from_numpy(np.ascontiguousarray(band.ravel())).to(device)
+                    self.keep.append(band_dev)
+                    p.band[c][mu] = band_dev.data_ptr()
+                if phis is None:
+                    E, P1, P2 = adr_precompute_phi(A_dev, w.tau, stream=stream)
+                else:
+                    E, P1, P2 = (to_device_f64(phis[c][j][mu], device) for j in range(3))
+                self.keep += [E, P1, P2]
+                for j, t in enumerate((E, P1, P2)):
+                    p.phi[c][j][mu] = t.data_ptr()
+        self.problem = p
+        nbytes = adr_workspace_bytes(p)
+        if nbytes == 0:
+            raise AdrError(ADR_EINVAL, "adr_workspace_bytes")
+        self.work = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=device)
+
+    def phi_host(self, c: int, j: int, mu: int) -> np.ndarray:
+        """Download one small matrix (column-major n x n) for inspection."""
+        n = self.shape[mu]
+        t = torch.empty(n * n, dtype=torch.float64, device=self.device)
+        ptr = self.problem.phi[c][j][mu]
+        adr_device_copy(ptr, t, n * n, self.stream)
+        torch.cuda.synchronize()
+        return from_device(t, (n, n))
+
+    def upload(self, U: np.ndarray, V: np.ndarray):
+        return to_device_f64(U, self.device), to_device_f64(V, self.device)
+
+    def download(self, U_dev, V_dev):
+        return from_device(U_dev, self.shape), from_device(V_dev, self.shape)
+
+    def step(self, U_dev, V_dev):
+        adr_step(self.problem, U_dev, V_dev, self.work, self.stream)
+
+    def solve(self, U_dev, V_dev, nsteps: int):
+        adr_solve(self.problem, U_dev, V_dev, nsteps, self.work, self.stream)
+
+
+__all__ = [n for n in dir() if n.startswith(("adr_", "ADR_"))] + [
+    "AdrProblem", "AdrError", "Solver", "to_device_f64", "from_device", "EXPORTED", "LIB_PATH"]

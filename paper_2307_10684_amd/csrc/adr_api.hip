@@ -1,0 +1,638 @@
+// Host side of libadr.so: argument validation, workspace carving, the launch
+// sequence of one ETD2RKds / Lawson2b step, the on-device matrix-function
+// precompute, and kernel timing.  Implements include/adr.h.
+#include "adr.h"
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+using namespace adr;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// ------------------------------------------------------------------ timing
+struct TimingRec {
+  int kind;
+  int slot;
+};
+struct Timing {
+  int capacity = 0;
+  std::vector<hipEvent_t> pool;  // 2 events per slot
+  std::vector<TimingRec> recs;
+} g_timing;
+
+template <class F>
+hipError_t timed(int kind, hipStream_t s, F&& f) {
+  Timing& t = g_timing;
+  if (t.capacity == 0 || (int)t.recs.size() >= t.capacity) return f();
+  const int slot = (int)t.recs.size();
+  hipError_t e = hipEventRecord(t.pool[2 * slot], s);
+  if (e != hipSuccess) return e;
+  e = f();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(t.pool[2 * slot + 1], s);
+  if (e != hipSuccess) return e;
+  t.recs.push_back({kind, slot});
+  return hipSuccess;
+}
+constexpr int kKindMode = 0, kKindStage = 1;
+
+inline int dev_err(hipError_t e) { return e == hipSuccess ? ADR_OK : ADR_EDEVICE; }
+
+// ------------------------------------------------------------------ mode products
+struct Geometry {
+  int d;
+  int n[3];
+  long long N;
+};
+
+bool mode_geometry(const Geometry& g, int mu, long long& L, long long& R) {
+  L = 1;
+  R = 1;
+  for (int nu = 0; nu < mu; ++nu) L *= g.n[nu];
+  for (int nu = mu + 1; nu < g.d; ++nu) R *= g.n[nu];
+  return true;
+}
+
+struct TuckerGroup {
+  int count = 0;
+  const void* in[kMaxGroup] = {};
+  const double* M[kMaxGroup][3] = {};
+  void* out[kMaxGroup] = {};
+  const double* Y[kMaxGroup] = {};
+  void* t1[kMaxGroup] = {};   // ping buffer
+  void* t2[kMaxGroup] = {};   // pong buffer (may be the input when it may be clobbered)
+};
+
+hipError_t launch_mode(const ModeArgs& a, int precision, int in_f32, int out_f32, hipStream_t s) {
+  if (precision == ADR_F64) return launch_mode_product_f64(a, s);
+  if (precision == ADR_F32) return launch_mode_product_f32(a, in_f32, out_f32, s);
+  return launch_mode_product_bf16x3(a, in_f32, out_f32, s);
+}
+
+// out = alpha * Tucker(in; M_1..M_d) + beta * Y for every tensor of the group, applied
+// mu = 1..d.  In reduced precision the intermediates are FP32 and the last
+// product writes FP64.
+hipError_t run_tucker(const Geometry& g, const TuckerGroup& tg, double alpha, double beta,
+                      int precision, hipStream_t s) {
+  const bool lowp = precision != ADR_F64;
+  for (int mu = 0; mu < g.d; ++mu) {
+    ModeArgs a{};
+    const bool last = (mu == g.d - 1);
+    for (int k = 0; k < tg.count; ++k) {
+      a.W[k] = (mu == 0) ? tg.in[k] : ((mu % 2 == 1) ? tg.t1[k] : tg.t2[k]);
+      a.out[k] = last ? tg.out[k] : ((mu % 2 == 0) ? tg.t1[k] : tg.t2[k]);
+      a.M[k] = tg.M[k][mu];
+      a.Y[k] = last ? tg.Y[k] : nullptr;
+      a.Z[k] = nullptr;
+    }
+    a.alpha = last ? alpha : 1.0;
+    a.beta = last ? beta : 0.0;
+    a.gamma = 0.0;
+    mode_geometry(g, mu, a.L, a.R);
+    a.X = a.L * a.R;
+    a.n = g.n[mu];
+    a.group = tg.count;
+    const int in_f32 = lowp ? 1 : 0;
+    const int out_f32 = (lowp && !last) ? 1 : 0;
+    hipError_t e = timed(kKindMode, s, [&] { return launch_mode(a, precision, in_f32, out_f32, s); });
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// ------------------------------------------------------------------ problem checks
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+int check_problem(const adr_problem* p, Geometry& g) {
+  if (!p) return ADR_EINVAL;
+  if (p->d < 1 || p->d > ADR_MAX_DIM) return ADR_EINVAL;
+  if (p->model < ADR_SCHNAKENBERG || p->model > ADR_ZERO) return ADR_EINVAL;
+  if (p->scheme != ADR_ETD2RKDS && p->scheme != ADR_LAWSON2B) return ADR_EINVAL;
+  if (p->precision < ADR_F64 || p->precision > ADR_BF16X3) return ADR_EINVAL;
+  if (p->flags != 0) return ADR_EINVAL;
+  if (!finite_pos(p->tau)) return ADR_EINVAL;
+  for (int i = 0; i < 8; ++i)
+    if (!std::isfinite(p->params[i])) return ADR_EINVAL;
+  g.d = p->d;
+  g.N = 1;
+  for (int mu = 0; mu < 3; ++mu) g.n[mu] = 1;
+  for (int mu = 0; mu < p->d; ++mu) {
+    if (p->n[mu] < 3 || p->n[mu] > 4096) return ADR_EINVAL;
+    g.n[mu] = p->n[mu];
+    g.N *= p->n[mu];
+  }
+  if (g.N > (1LL << 31)) return ADR_EINVAL;
+  for (int c = 0; c < 2; ++c)
+    for (int mu = 0; mu < p->d; ++mu) {
+      if (p->scheme == ADR_ETD2RKDS) {
+        if (!p->phi[c][1][mu] || !p->phi[c][2][mu]) return ADR_EINVAL;
+        if (!p->band[c][mu] && !p->dense[c][mu]) return ADR_EINVAL;
+      } else {
+        if (!p->phi[c][0][mu]) return ADR_EINVAL;
+      }
+    }
+  return ADR_OK;
+}
+
+// Workspace carve-up.  Tensors are FP64 (8 bytes) or FP32 (4 bytes) for the
+// reduced-precision intermediates; reduced-precision modes also hold FP32
+// copies of the small matrices.
+struct Carve {
+  double* U2 = nullptr;
+  double* V2 = nullptr;
+  void* R[4] = {};
+  void* T[4] = {};
+  float* phi32[2][3][3] = {};
+  size_t bytes = 0;
+};
+
+Carve carve(const adr_problem* p, const Geometry& g, char* base) {
+  Carve c;
+  const bool lowp = p->precision != ADR_F64;
+  const size_t tb64 = align_up((size_t)g.N * sizeof(double));
+  const size_t tbw = align_up((size_t)g.N * (lowp ? sizeof(float) : sizeof(double)));
+  size_t off = 0;
+  auto take = [&](size_t b) -> void* {
+    void* ptr = base ? static_cast<void*>(base + off) : nullptr;
+    off += b;
+    return ptr;
+  };
+  c.U2 = static_cast<double*>(take(tb64));
+  c.V2 = static_cast<double*>(take(tb64));
+  const int nin = (p->scheme == ADR_LAWSON2B) ? 4 : 2;
+  for (int k = 0; k < nin; ++k) c.R[k] = take(tbw);
+  if (g.d >= 2)
+    for (int k = 0; k < nin; ++k) c.T[k] = take(tbw);
+  if (lowp) {
+    for (int cc = 0; cc < 2; ++cc)
+      for (int j = 0; j < 3; ++j)
+        for (int mu = 0; mu < g.d; ++mu)
+          c.phi32[cc][j][mu] =
+              static_cast<float*>(take(align_up((size_t)g.n[mu] * g.n[mu] * sizeof(float))));
+  }
+  c.bytes = off;
+  return c;
+}
+
+Reaction reaction_of(const adr_problem* p) {
+  Reaction r{};
+  r.model = p->model;
+  for (int i = 0; i < 8; ++i) r.p[i] = p->params[i];
+  return r;
+}
+
+// Prepare reduced-precision copies of the small matrices (once per step call).
+hipError_t prepare_lowp(const adr_problem* p, const Geometry& g, const Carve& c, hipStream_t s) {
+  if (p->precision == ADR_F64) return hipSuccess;
+  for (int cc = 0; cc < 2; ++cc)
+    for (int j = 0; j < 3; ++j)
+      for (int mu = 0; mu < g.d; ++mu) {
+        const double* src = p->phi[cc][j][mu];
+        if (!src) continue;
+        hipError_t e = launch_convert_f64_f32(src, c.phi32[cc][j][mu], (size_t)g.n[mu] * g.n[mu], s);
+        if (e != hipSuccess) return e;
+      }
+  return hipSuccess;
+}
+
+const double* phi_ptr(const adr_problem* p, const Carve& c, int comp, int j, int mu) {
+  if (p->precision == ADR_F64) return p->phi[comp][j][mu];
+  return reinterpret_cast<const double*>(c.phi32[comp][j][mu]);
+}
+
+hipError_t step_etd2rkds(const adr_problem* p, const Geometry& g, const Carve& c, double* U,
+                         double* V, hipStream_t s) {
+  const bool lowp = p->precision != ADR_F64;
+  const Reaction r = reaction_of(p);
+  StageGeom sg{};
+  sg.d = g.d;
+  sg.N = g.N;
+  for (int mu = 0; mu < 3; ++mu) sg.n[mu] = g.n[mu];
+  bool dense_needed = false;
+  for (int cc = 0; cc < 2; ++cc)
+    for (int mu = 0; mu < g.d; ++mu) {
+      sg.band[cc][mu] = p->band[cc][mu];
+      if (!p->band[cc][mu]) dense_needed = true;
+    }
+  if (dense_needed && lowp) return hipErrorNotSupported;
+  // stage 1: R^c = K^c C_n + G^c(U_n, V_n)
+  hipError_t e = timed(kKindStage, s, [&] {
+    return launch_etd_stage1(sg, r, U, V, c.R[0], c.R[1], lowp ? 1 : 0, s);
+  });
+  if (e != hipSuccess) return e;
+  if (dense_needed) {
+    // directions without a band: R^c += C x_mu A_mu^c with the dense matrix (FP64 only)
+    for (int mu = 0; mu < g.d; ++mu) {
+      ModeArgs a{};
+      int k = 0;
+      for (int cc = 0; cc < 2; ++cc) {
+        if (p->band[cc][mu]) continue;
+        a.W[k] = cc == 0 ? U : V;
+        a.M[k] = p->dense[cc][mu];
+        a.out[k] = c.R[cc];
+        a.Y[k] = static_cast<const double*>(c.R[cc]);
+        ++k;
+      }
+      if (k == 0) continue;
+      a.group = k;
+      a.alpha = 1.0;
+      a.beta = 1.0;
+      mode_geometry(g, mu, a.L, a.R);
+      a.X = a.L * a.R;
+      a.n = g.n[mu];
+      e = timed(kKindMode, s, [&] { return launch_mode_product_f64(a, s); });
+      if (e != hipSuccess) return e;
+    }
+  }
+  // C_{n2} = C_n + tau * Tucker(R^c; phi_1)
+  TuckerGroup tg;
+  tg.count = 2;
+  for (int cc = 0; cc < 2; ++cc) {
+    tg.in[cc] = c.R[cc];
+    tg.t1[cc] = c.T[cc];
+    tg.t2[cc] = c.R[cc];
+    for (int mu = 0; mu < g.d; ++mu) tg.M[cc][mu] = phi_ptr(p, c, cc, 1, mu);
+  }
+  tg.out[0] = c.U2;
+  tg.out[1] = c.V2;
+  tg.Y[0] = U;
+  tg.Y[1] = V;
+  e = run_tucker(g, tg, p->tau, 1.0, p->precision, s);
+  if (e != hipSuccess) return e;
+  // stage 2: R^c = G^c(U_{n2}, V_{n2}) - G^c(U_n, V_n)
+  e = timed(kKindStage, s, [&] {
+    return launch_etd_stage2(g.N, r, U, V, c.U2, c.V2, c.R[0], c.R[1], lowp ? 1 : 0, s);
+  });
+  if (e != hipSuccess) return e;
+  // C_{n+1} = C_{n2} + 2^(d-1) tau * Tucker(R^c; phi_2)
+  for (int cc = 0; cc < 2; ++cc)
+    for (int mu = 0; mu < g.d; ++mu) tg.M[cc][mu] = phi_ptr(p, c, cc, 2, mu);
+  tg.out[0] = U;
+  tg.out[1] = V;
+  tg.Y[0] = c.U2;
+  tg.Y[1] = c.V2;
+  const double scale = std::ldexp(p->tau, g.d - 1);
+  return run_tucker(g, tg, scale, 1.0, p->precision, s);
+}
+
+hipError_t step_lawson2b(const adr_problem* p, const Geometry& g, const Carve& c, double* U,
+                         double* V, hipStream_t s) {
+  const bool lowp = p->precision != ADR_F64;
+  const Reaction r = reaction_of(p);
+  // stage 1: A^c = C + tau G^c,  B^c = C + tau/2 G^c
+  hipError_t e = timed(kKindStage, s, [&] {
+    return launch_lawson_stage1(g.N, r, p->tau, U, V, c.R[0], c.R[1], c.R[2], c.R[3],
+                                lowp ? 1 : 0, s);
+  });
+  if (e != hipSuccess) return e;
+  // C_{n2} = Tucker(A^c; e^{tau A^c}),  C <- Tucker(B^c; e^{tau A^c}) in one grouped pass
+  TuckerGroup tg;
+  tg.count = 4;
+  for (int k = 0; k < 4; ++k) {
+    const int cc = k & 1;
+    tg.in[k] = c.R[k];
+    tg.t1[k] = c.T[k];
+    tg.t2[k] = c.R[k];
+    for (int mu = 0; mu < g.d; ++mu) tg.M[k][mu] = phi_ptr(p, c, cc, 0, mu);
+  }
+  tg.out[0] = c.U2;
+  tg.out[1] = c.V2;
+  tg.out[2] = U;
+  tg.out[3] = V;
+  e = run_tucker(g, tg, 1.0, 0.0, p->precision, s);
+  if (e != hipSuccess) return e;
+  // stage 2: C_{n+1} = Tucker(B^c; e^{tau A^c}) + tau/2 G^c(U_{n2}, V_{n2})
+  return timed(kKindStage, s, [&] {
+    return launch_lawson_stage2(g.N, r, p->tau, U, V, c.U2, c.V2, s);
+  });
+}
+
+int do_steps(const adr_problem* p, double* U, double* V, int nsteps, void* work,
+             size_t work_bytes, void* stream) {
+  Geometry g{};
+  int st = check_problem(p, g);
+  if (st != ADR_OK) return st;
+  if (!U || !V || nsteps < 0) return ADR_EINVAL;
+  const Carve need = carve(p, g, nullptr);
+  if (!work || work_bytes < need.bytes) return ADR_ENOMEM;
+  if (reinterpret_cast<uintptr_t>(work) % kAlign != 0) return ADR_EINVAL;
+  if (p->scheme == ADR_ETD2RKDS && p->precision != ADR_F64)
+    for (int cc = 0; cc < 2; ++cc)
+      for (int mu = 0; mu < p->d; ++mu)
+        if (!p->band[cc][mu]) return ADR_ENOTSUP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Carve c = carve(p, g, static_cast<char*>(work));
+  hipError_t e = prepare_lowp(p, g, c, s);
+  if (e != hipSuccess) return ADR_EDEVICE;
+  for (int it = 0; it < nsteps; ++it) {
+    e = (p->scheme == ADR_ETD2RKDS) ? step_etd2rkds(p, g, c, U, V, s)
+                                    : step_lawson2b(p, g, c, U, V, s);
+    if (e == hipErrorNotSupported) return ADR_ENOTSUP;
+    if (e != hipSuccess) return ADR_EDEVICE;
+  }
+  return ADR_OK;
+}
+
+// ------------------------------------------------------------------ precompute helpers
+hipError_t gemm(int n, const double* A, const double* B, double* C, double alpha, double beta,
+                const double* Y, double gamma, const double* Z, hipStream_t s) {
+  // C = alpha * A B + beta * Y + gamma * Z  as the mode-1 product of the 2-tensor B by A
+  ModeArgs a{};
+  a.W[0] = B;
+  a.M[0] = A;
+  a.out[0] = C;
+  a.Y[0] = Y;
+  a.Z[0] = Z;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.gamma = gamma;
+  a.L = 1;
+  a.R = n;
+  a.X = n;
+  a.n = n;
+  a.group = 1;
+  return launch_mode_product_f64(a, s);
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+const char* adr_strerror(int status) {
+  switch (status) {
+    case ADR_OK: return "ok";
+    case ADR_EINVAL: return "invalid argument";
+    case ADR_ENOMEM: return "workspace too small or allocation failed";
+    case ADR_EDEVICE: return "HIP device error";
+    case ADR_ENOTSUP: return "unsupported combination";
+    case ADR_ENONFINITE: return "non-finite value";
+    default: return "unknown status";
+  }
+}
+
+int adr_version(void) { return 10000; }
+
+int adr_build_1d_ops(int n, double a, double b, double diff, double vel, int bc, double* A,
+                     double* band) {
+  if (n < 3 || !std::isfinite(a) || !std::isfinite(b) || !(b > a)) return ADR_EINVAL;
+  if (!std::isfinite(diff) || !std::isfinite(vel)) return ADR_EINVAL;
+  if (bc != ADR_BC_NEUMANN) return ADR_EINVAL;
+  if (!A && !band) return ADR_EINVAL;
+  const double h = (b - a) / (n - 1);
+  const double dif = diff / (h * h);   // diffusion weight
+  const double adv = vel / (2.0 * h);  // centred advection weight
+  std::vector<double> lo(n, 0.0), di(n, 0.0), up(n, 0.0);
+  for (int i = 1; i < n - 1; ++i) {
+    lo[i] = dif + adv;   // coefficient of u_{i-1}: diff/h^2 - vel * (-1/(2h))
+    di[i] = -2.0 * dif;
+    up[i] = dif - adv;   // coefficient of u_{i+1}: diff/h^2 - vel * (1/(2h))
+  }
+  // Neumann ghost rows: u_{-1} = u_1, u_n = u_{n-2}; the centred advection cancels
+  di[0] = -2.0 * dif;
+  up[0] = 2.0 * dif;
+  di[n - 1] = -2.0 * dif;
+  lo[n - 1] = 2.0 * dif;
+  if (A) {
+    std::memset(A, 0, sizeof(double) * (size_t)n * n);
+    for (int i = 0; i < n; ++i) {
+      A[i + (size_t)n * i] = di[i];
+      if (i > 0) A[i + (size_t)n * (i - 1)] = lo[i];
+      if (i < n - 1) A[i + (size_t)n * (i + 1)] = up[i];
+    }
+  }
+  if (band) {
+    for (int i = 0; i < n; ++i) {
+      band[i] = lo[i];
+      band[n + i] = di[i];
+      band[2 * n + i] = up[i];
+    }
+  }
+  return ADR_OK;
+}
+
+int adr_precompute_phi(int n, const double* A_dev, double tau, double* E_dev, double* P1_dev,
+                       double* P2_dev, void* stream) {
+  if (n < 1 || n > 4096 || !A_dev || !std::isfinite(tau) || tau == 0.0) return ADR_EINVAL;
+  if (!E_dev && !P1_dev && !P2_dev) return ADR_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t nn = (size_t)n * n;
+  // buffers: Y^1..Y^6, block B, Horner H, current E/P1/P2, next E/P1/P2, norm
+  constexpr int kBuf = 14;
+  double* base = nullptr;
+  if (hipMalloc(&base, sizeof(double) * (nn * kBuf + 1)) != hipSuccess) return ADR_ENOMEM;
+  double* Yp[7];
+  for (int j = 1; j <= 6; ++j) Yp[j] = base + nn * (j - 1);
+  double* Bb = base + nn * 6;
+  double* H = base + nn * 7;
+  double* cur[3] = {base + nn * 8, base + nn * 9, base + nn * 10};
+  double* nxt[3] = {base + nn * 11, base + nn * 12, base + nn * 13};
+  double* dnorm = base + nn * kBuf;
+  int status = ADR_OK;
+  auto fail = [&](int st) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(base);
+    return st;
+  };
+  // ||tau A||_1 sets the scaling power s with ||tau A / 2^s||_1 <= 1
+  if (launch_norm1(n, A_dev, tau, dnorm, s) != hipSuccess) return fail(ADR_EDEVICE);
+  double norm = 0.0;
+  if (hipMemcpyAsync(&norm, dnorm, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return fail(ADR_EDEVICE);
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(ADR_EDEVICE);
+  if (!std::isfinite(norm)) return fail(ADR_ENONFINITE);
+  int sq = 0;
+  if (norm > 1.0) sq = (int)std::ceil(std::log2(norm));
+  const double scale = std::ldexp(tau, -sq);
+  hipError_t e = launch_scale_copy((long long)nn, A_dev, scale, Yp[1], s);
+  for (int j = 2; j <= 6 && e == hipSuccess; ++j)
+    e = gemm(n, Yp[j - 1], Yp[1], Yp[j], 1.0, 0.0, nullptr, 0.0, nullptr, s);
+  if (e != hipSuccess) return fail(ADR_EDEVICE);
+  // Taylor polynomials of degree 18 of exp, phi_1, phi_2 (coefficients 1/(k+l)!) in
+  // Paterson-Stockmeyer form: p = B0 + (B1 + (B2 + c18 Y^6) Y^6) Y^6, Bj = sum_i c_{6j+i} Y^i
+  for (int l = 0; l < 3 && e == hipSuccess; ++l) {
+    double coef[19];
+    double f = 1.0;
+    for (int j = 1; j <= l; ++j) f *= j;  // l!
+    for (int k = 0; k <= 18; ++k) {
+      coef[k] = 1.0 / f;                  // 1/(k+l)!
+      f *= (double)(k + l + 1);
+    }
+    auto block = [&](int j, double* out, bool add_top) {
+      const double* P[8];
+      double c[8];
+      int cnt = 0;
+      for (int i = 1; i <= 5; ++i) {
+        P[cnt] = Yp[i];
+        c[cnt] = coef[6 * j + i];
+        ++cnt;
+      }
+      if (add_top) {
+        P[cnt] = Yp[6];
+        c[cnt] = coef[18];
+        ++cnt;
+      }
+      return launch_lincomb(n, cnt, P, c, coef[6 * j], out, s);
+    };
+    e = block(2, H, true);                                                           // H = B2 + c18 Y^6
+    if (e == hipSuccess) e = block(1, Bb, false);                                    // B1
+    if (e == hipSuccess) e = gemm(n, H, Yp[6], nxt[l], 1.0, 1.0, Bb, 0.0, nullptr, s);  // H Y^6 + B1
+    if (e == hipSuccess) e = block(0, Bb, false);                                    // B0
+    if (e == hipSuccess) e = gemm(n, nxt[l], Yp[6], cur[l], 1.0, 1.0, Bb, 0.0, nullptr, s);
+  }
+  if (e != hipSuccess) return fail(ADR_EDEVICE);
+  // modified squaring: e^{2X} = (e^X)^2, phi_1(2X) = (e^X phi_1 + phi_1)/2,
+  // phi_2(2X) = (e^X phi_2 + phi_1 + phi_2)/4
+  for (int it = 0; it < sq && e == hipSuccess; ++it) {
+    e = gemm(n, cur[0], cur[2], nxt[2], 0.25, 0.25, cur[1], 0.25, cur[2], s);
+    if (e == hipSuccess) e = gemm(n, cur[0], cur[1], nxt[1], 0.5, 0.5, cur[1], 0.0, nullptr, s);
+    if (e == hipSuccess) e = gemm(n, cur[0], cur[0], nxt[0], 1.0, 0.0, nullptr, 0.0, nullptr, s);
+    for (int j = 0; j < 3; ++j) std::swap(cur[j], nxt[j]);
+  }
+  double* outs[3] = {E_dev, P1_dev, P2_dev};
+  for (int j = 0; j < 3 && e == hipSuccess; ++j)
+    if (outs[j]) e = launch_copy_f64(cur[j], outs[j], nn, s);
+  if (e != hipSuccess) return fail(ADR_EDEVICE);
+  if (hipStreamSynchronize(s) != hipSuccess) status = ADR_EDEVICE;
+  (void)hipFree(base);
+  return status;
+}
+
+size_t adr_workspace_bytes(const adr_problem* p) {
+  Geometry g{};
+  if (check_problem(p, g) != ADR_OK) return 0;
+  return carve(p, g, nullptr).bytes;
+}
+
+int adr_step(const adr_problem* p, double* U, double* V, void* work, size_t work_bytes,
+             void* stream) {
+  return do_steps(p, U, V, 1, work, work_bytes, stream);
+}
+
+int adr_solve(const adr_problem* p, double* U, double* V, int nsteps, void* work,
+              size_t work_bytes, void* stream) {
+  return do_steps(p, U, V, nsteps, work, work_bytes, stream);
+}
+
+int adr_mode_product(int d, const int32_t* n, int mu, const double* M, const double* W,
+                     double* out, double alpha, double beta, const double* Y, void* stream) {
+  if (d < 1 || d > ADR_MAX_DIM || !n || mu < 0 || mu >= d || !M || !W || !out) return ADR_EINVAL;
+  if (!std::isfinite(alpha) || (Y && !std::isfinite(beta))) return ADR_EINVAL;
+  if (out == W) return ADR_EINVAL;
+  Geometry g{};
+  g.d = d;
+  g.N = 1;
+  for (int k = 0; k < 3; ++k) g.n[k] = 1;
+  for (int k = 0; k < d; ++k) {
+    if (n[k] < 1 || n[k] > 1 << 20) return ADR_EINVAL;
+    g.n[k] = n[k];
+    g.N *= n[k];
+  }
+  if (g.N > (1LL << 31) || n[mu] > 4096) return ADR_EINVAL;
+  ModeArgs a{};
+  a.W[0] = W;
+  a.M[0] = M;
+  a.out[0] = out;
+  a.Y[0] = Y;
+  a.alpha = alpha;
+  a.beta = Y ? beta : 0.0;
+  mode_geometry(g, mu, a.L, a.R);
+  a.X = a.L * a.R;
+  a.n = n[mu];
+  a.group = 1;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return dev_err(timed(kKindMode, s, [&] { return launch_mode_product_f64(a, s); }));
+}
+
+size_t adr_tucker_workspace_bytes(int d, const int32_t* n) {
+  if (d < 1 || d > ADR_MAX_DIM || !n) return 0;
+  long long N = 1;
+  for (int k = 0; k < d; ++k) {
+    if (n[k] < 1) return 0;
+    N *= n[k];
+  }
+  return 2 * align_up((size_t)N * sizeof(double));
+}
+
+int adr_tucker(int d, const int32_t* n, const double* const* M, const double* W, double* out,
+               double alpha, double beta, const double* Y, void* work, size_t work_bytes,
+               void* stream) {
+  if (d < 1 || d > ADR_MAX_DIM || !n || !M || !W || !out || out == W) return ADR_EINVAL;
+  if (!std::isfinite(alpha) || (Y && !std::isfinite(beta))) return ADR_EINVAL;
+  Geometry g{};
+  g.d = d;
+  g.N = 1;
+  for (int k = 0; k < 3; ++k) g.n[k] = 1;
+  for (int k = 0; k < d; ++k) {
+    if (n[k] < 1 || n[k] > 4096 || !M[k]) return ADR_EINVAL;
+    g.n[k] = n[k];
+    g.N *= n[k];
+  }
+  if (g.N > (1LL << 31)) return ADR_EINVAL;
+  const size_t need = adr_tucker_workspace_bytes(d, n);
+  if (d > 1 && (!work || work_bytes < need)) return ADR_ENOMEM;
+  TuckerGroup tg;
+  tg.count = 1;
+  tg.in[0] = W;
+  tg.out[0] = out;
+  tg.Y[0] = Y;
+  if (d > 1) {
+    tg.t1[0] = work;
+    tg.t2[0] = static_cast<char*>(work) + need / 2;
+  }
+  for (int k = 0; k < d; ++k) tg.M[0][k] = M[k];
+  return dev_err(run_tucker(g, tg, alpha, Y ? beta : 0.0, ADR_F64, static_cast<hipStream_t>(stream)));
+}
+
+int adr_device_copy(const double* in, double* out, size_t count, void* stream) {
+  if (!in || !out) return ADR_EINVAL;
+  if (count == 0) return ADR_OK;
+  return dev_err(launch_copy_f64(in, out, count, static_cast<hipStream_t>(stream)));
+}
+
+int adr_timing_enable(int capacity) {
+  if (capacity < 0) return ADR_EINVAL;
+  Timing& t = g_timing;
+  for (hipEvent_t ev : t.pool) (void)hipEventDestroy(ev);
+  t.pool.clear();
+  t.recs.clear();
+  t.capacity = 0;
+  if (capacity == 0) return ADR_OK;
+  t.pool.resize(2 * (size_t)capacity);
+  for (auto& ev : t.pool)
+    if (hipEventCreate(&ev) != hipSuccess) {
+      ev = nullptr;
+      return ADR_EDEVICE;
+    }
+  t.capacity = capacity;
+  return ADR_OK;
+}
+
+int adr_timing_read(int kind, int* launches, double* total_ms) {
+  if (!launches || !total_ms || kind < 0 || kind > 2) return ADR_EINVAL;
+  Timing& t = g_timing;
+  int cnt = 0;
+  double tot = 0.0;
+  for (const TimingRec& r : t.recs) {
+    if (kind != 2 && r.kind != kind) continue;
+    hipEvent_t a = t.pool[2 * r.slot], b = t.pool[2 * r.slot + 1];
+    if (hipEventSynchronize(b) != hipSuccess) return ADR_EDEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return ADR_EDEVICE;
+    ++cnt;
+    tot += ms;
+  }
+  *launches = cnt;
+  *total_ms = tot;
+  return ADR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// Internal declarations shared by the host library and the HIP kernels.
+// Nothing here is part of the public ABI (include/adr.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace adr {
+
+// Up to four tensors share one geometry in a grouped mode-product launch
+// (both components of ETD2RKds; both components and both Tucker inputs of
+// Lawson2b).
+constexpr int kMaxGroup = 4;
+
+enum class Elem : int { F64 = 0, F32 = 1 };
+
+// Geometry of one mu-mode product on an order-d tensor stored first index
+// fastest: the tensor is viewed as (L, n, R) with L = prod_{nu<mu} n_nu,
+// R = prod_{nu>mu} n_nu.  A fibre index x in [0, L*R) stands for (l, r) with
+// x = l + L*r, and element k of fibre x sits at l + L*(k + n*r).
+struct ModeArgs {
+  const void* W[kMaxGroup];      // input tensors (Elem in_t)
+  const void* M[kMaxGroup];      // n x n column-major matrices (FP64, or FP32 for the F32 path)
+  void* out[kMaxGroup];          // output tensors (Elem out_t)
+  const double* Y[kMaxGroup];    // optional FP64 addends (may alias out when out_t is F64)
+  const double* Z[kMaxGroup];    // optional second FP64 addends
+  double alpha, beta, gamma;     // out = alpha*(W x_mu M) + beta*Y + gamma*Z
+  long long L, R, X;             // X = L*R fibres
+  int n;                         // n_mu (fibre length, matrix size)
+  int group;                     // number of tensors in the launch (1..kMaxGroup)
+};
+
+// Launchers (return hipSuccess or the launch error).
+hipError_t launch_mode_product_f64(const ModeArgs& a, hipStream_t s);
+hipError_t launch_mode_product_f32(const ModeArgs& a, int in_f32, int out_f32, hipStream_t s);
+hipError_t launch_mode_product_bf16x3(const ModeArgs& a, int in_f32, int out_f32, hipStream_t s);
+
+// Reaction model constants as passed to the stage kernels.
+struct Reaction {
+  int model;
+  double p[8];
+};
+
+struct StageGeom {
+  int d;
+  int n[3];
+  long long N;
+  const double* band[2][3];   // tridiagonal bands (sub, diag, super) per component/direction, or null
+};
+
+// ETD2RKds stage 1: R^c = sum_mu C x_mu A_mu^c (stencil where a band is given,
+// nothing where it is not) + G^c(U, V).  R may be FP64 or FP32.
+hipError_t launch_etd_stage1(const StageGeom& g, const Reaction& r, const double* U,
+                             const double* V, void* Ru, void* Rv, int r_f32, hipStream_t s);
+// ETD2RKds stage 2: R^c = G^c(U2, V2) - G^c(U, V).
+hipError_t launch_etd_stage2(long long N, const Reaction& r, const double* U, const double* V,
+                             const double* U2, const double* V2, void* Ru, void* Rv, int r_f32,
+                             hipStream_t s);
+// Lawson2b stage 1: A^c = C + tau G^c(U, V), B^c = C + tau/2 G^c(U, V).
+hipError_t launch_lawson_stage1(long long N, const Reaction& r, double tau, const double* U,
+                                const double* V, void* Au, void* Av, void* Bu, void* Bv, int f32,
+                                hipStream_t s);
+// Lawson2b stage 2: C += tau/2 G^c(U2, V2)  (C holds the second Tucker result).
+hipError_t launch_lawson_stage2(long long N, const Reaction& r, double tau, double* U, double* V,
+                                const double* U2, const double* V2, hipStream_t s);
+
+// Small dense helpers for the matrix-function precompute (n x n, column-major).
+hipError_t launch_norm1(int n, const double* X, double scale, double* out, hipStream_t s);
+hipError_t launch_scale_copy(long long count, const double* in, double scale, double* out,
+                             hipStream_t s);
+// out = sum_j c[j] * P[j] + c0 * I   (up to 8 matrices)
+hipError_t launch_lincomb(int n, int count, const double* const* P, const double* c, double c0,
+                          double* out, hipStream_t s);
+hipError_t launch_copy_f64(const double* in, double* out, size_t count, hipStream_t s);
+hipError_t launch_convert_f64_f32(const double* in, float* out, size_t count, hipStream_t s);
+
+}  // namespace adr

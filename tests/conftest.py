@@ -28,3 +28,21 @@ def pytest_collection_modifyitems(config, items):
     for item in items:
         if "slow" in item.keywords:
             item.add_marker(skip)
+
+
+@pytest.fixture(scope="session")
+def adr():
+    """The HIP binding, built first if the library is missing."""
+    from paper_2307_10684_amd import build as _build
+    if not os.path.exists(_build.LIB):
+        _build.build()
+    import paper_2307_10684_amd
+    return paper_2307_10684_amd
+
+
+@pytest.fixture(scope="session")
+def dev(adr):
+    """The GPU binding; fails (does not skip) when no GPU is visible."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X (run them with -m gpu on the GPU box)"
+    return adr

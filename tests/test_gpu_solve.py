@@ -1,0 +1,133 @@
+"""GPU parity of whole ETD2RKds (Sec. 3, eq. (11)) and Lawson2b (Sec. 2,
+eq. (7)) steps against the FP64 oracle, called through the C ABI.
+
+Two kinds of runs:
+* hot path: the GPU steps with the oracle's small matrices, so the comparison
+  isolates the stage kernels and the mode products;
+* end to end: the GPU also builds its operators (adr_build_1d_ops) and its
+  matrix functions (adr_precompute_phi), as a user would.
+Gate: relative infinity-norm error <= 1e-12 per component (FP64)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth as S
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _oracle(w, seed, steps, scheme="etd2rkds"):
+    p = O.problem_from_workload(w)
+    mats = O.precompute(p)
+    U0, V0 = S.initial_state(w, seed)
+    U, V = O.solve(U0, V0, p, steps, scheme, mats=mats)
+    return U0, V0, U, V, mats
+
+
+def _gpu(dev, w, U0, V0, steps, scheme="etd2rkds", mats=None, use_band=True, chunks=None):
+    import torch
+    s = dev.Solver(w, scheme=scheme, phis=mats, use_band=use_band)
+    Ud, Vd = s.upload(U0, V0)
+    for k in (chunks or [steps]):
+        s.solve(Ud, Vd, k)
+    torch.cuda.synchronize()
+    return s.download(Ud, Vd)
+
+
+def _assert_close(got, ref, tol=TOL):
+    eu = O.rel_inf_error(got[0], ref[0])
+    ev = O.rel_inf_error(got[1], ref[1])
+    assert eu <= tol and ev <= tol, (eu, ev)
+    return max(eu, ev)
+
+
+CASES = [
+    ("schnakenberg2d_64x64_100", S.schnakenberg_2d(64, 100), 100),
+    ("schnakenberg2d_130x70_30", S.with_shape(S.schnakenberg_2d(), (130, 70)), 30),
+    ("fhn3d_40x36x44_20", S.with_shape(S.fhn_3d(), (40, 36, 44)), 20),
+    ("bruss3d_72x40x150_10", S.with_shape(S.brusselator_3d(), (72, 40, 150)), 10),
+    ("bruss1d_300_50", S.with_shape(S.brusselator_3d(), (300,)), 50),
+    ("fhn3d_3x3x3_5", S.with_shape(S.fhn_3d(), (3, 3, 3)), 5),
+]
+
+
+@pytest.mark.parametrize("name,w,steps", CASES, ids=[c[0] for c in CASES])
+def test_etd2rkds_hot_path(dev, name, w, steps):
+    U0, V0, U, V, mats = _oracle(w, 0, steps)
+    got = _gpu(dev, w, U0, V0, steps, mats=mats)
+    _assert_close(got, (U, V))
+
+
+@pytest.mark.parametrize("name,w,steps", CASES[:4], ids=[c[0] for c in CASES[:4]])
+def test_etd2rkds_end_to_end(dev, name, w, steps):
+    U0, V0, U, V, _ = _oracle(w, 1, steps)
+    got = _gpu(dev, w, U0, V0, steps)
+    _assert_close(got, (U, V))
+
+
+@pytest.mark.parametrize("name,w,steps", CASES[:4], ids=[c[0] for c in CASES[:4]])
+def test_lawson2b(dev, name, w, steps):
+    U0, V0, U, V, mats = _oracle(w, 2, steps, "lawson2b")
+    got = _gpu(dev, w, U0, V0, steps, "lawson2b", mats=mats)
+    _assert_close(got, (U, V))
+
+
+@pytest.mark.parametrize("name,w,steps", [CASES[1], CASES[3]], ids=[CASES[1][0], CASES[3][0]])
+def test_dense_kronecker_action_path(dev, name, w, steps):
+    # without the tridiagonal bands the library applies K C with dense mode products
+    U0, V0, U, V, mats = _oracle(w, 3, steps)
+    got = _gpu(dev, w, U0, V0, steps, mats=mats, use_band=False)
+    _assert_close(got, (U, V))
+
+
+def test_full_size_fhn_128(dev):
+    w = S.fhn_3d()                           # 128^3, tau = 1e-3
+    U0, V0, U, V, mats = _oracle(w, 0, 2)
+    _assert_close(_gpu(dev, w, U0, V0, 2, mats=mats), (U, V))
+
+
+def test_full_size_brusselator_256(dev):
+    w = S.brusselator_3d()                   # 256^3, tau = 5e-3: the benchmark workload
+    U0, V0, U, V, mats = _oracle(w, 0, 1)
+    _assert_close(_gpu(dev, w, U0, V0, 1, mats=mats), (U, V))
+
+
+def test_full_size_brusselator_256_end_to_end(dev):
+    w = S.brusselator_3d()
+    U0, V0, U, V, _ = _oracle(w, 5, 1)
+    _assert_close(_gpu(dev, w, U0, V0, 1), (U, V))
+
+
+def test_largest_2d_grid(dev):
+    w = S.with_shape(S.schnakenberg_2d(), (1024, 1024))
+    U0, V0, U, V, mats = _oracle(w, 0, 1)
+    _assert_close(_gpu(dev, w, U0, V0, 1, mats=mats), (U, V))
+
+
+def test_bitwise_determinism_and_resume(dev):
+    w = S.with_shape(S.brusselator_3d(), (64, 48, 80))
+    U0, V0 = S.initial_state(w, 4)
+    a = _gpu(dev, w, U0, V0, 20)
+    b = _gpu(dev, w, U0, V0, 20)
+    c = _gpu(dev, w, U0, V0, 20, chunks=[7, 13])
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+
+
+@pytest.mark.parametrize("w", [S.schnakenberg_2d(64, 1), S.fhn_3d(48, 1), S.brusselator_3d(40, 1)],
+                         ids=lambda w: w.model)
+@pytest.mark.parametrize("scheme", ["etd2rkds", "lawson2b"])
+def test_homogeneous_steady_state_fixed(dev, w, scheme):
+    U0 = np.full(w.n, w.base[0], order="F")
+    V0 = np.full(w.n, w.base[1], order="F")
+    U, V = _gpu(dev, w, U0, V0, 100, scheme)
+    assert np.abs(U - w.base[0]).max() <= 1e-11 and np.abs(V - w.base[1]).max() <= 1e-11
+
+
+def test_zero_steps_leaves_state(dev):
+    w = S.with_shape(S.fhn_3d(), (20, 21, 22))
+    U0, V0 = S.initial_state(w, 0)
+    U, V = _gpu(dev, w, U0, V0, 0)
+    assert np.array_equal(U, U0) and np.array_equal(V, V0)
