@@ -1,0 +1,228 @@
+#!/usr/bin/env python3
+"""Benchmark of the ETD2RKds hot path on one MI355X.
+
+One "step" is one ETD2RKds step (Sec. 3, eq. (11)) of both components over
+the whole grid: two stage kernels and 2*d grouped mu-mode-product launches.
+Default workload: the 3D advective Brusselator on a 256^3 grid (tau = 5e-3,
+FP64), with seeded synthetic initial data already resident in HBM.
+
+Prints ONE JSON line with the throughput (grid-point-steps/s), the roofline
+position of the dominant kernel (the FP64 MFMA mode product, timed with HIP
+events on its own stream inside the timed pass), and the CPU oracle timed on
+the host's cores on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--precision f64]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-point-steps/s at 256³ (FP64 vs split-BF16/FP32) + p50/p99 solve latency"
+PEAKS = {  # published MI355X dense peaks
+    "f64_mfma_tflops": 78.6,
+    "f32_mfma_tflops": 157.3,
+    "bf16_mfma_tflops": 2500.0,
+    "hbm_gbs": 8000.0,
+}
+MODE_SRC = {"f64": "mode_product_f64.hip", "f32": "mode_product_lowp.hip",
+            "bf16x3": "mode_product_lowp.hip"}
+
+
+def _src_hash(name: str) -> str:
+    path = os.path.join(ROOT, "paper_2307_10684_amd", "csrc", name)
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic_from_profiles(precision: str, workload: str):
+    """HBM bytes per launch of the mode product from the committed counter summary,
+    or None if there is none or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"mode_product_{precision}_{workload}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != _src_hash(MODE_SRC[precision]):
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(workload, steps: int = 2):
+    """The oracle as it stands, timed on the host for a bounded number of steps."""
+    import numpy as np
+    import oracle as O
+    import synth as S
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    p = O.problem_from_workload(workload)
+    mats = O.precompute(p)
+    U, V = S.initial_state(workload, 0)
+    U, V = O.etd2rkds_step(U, V, p, mats)  # first touch outside the timing
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        U, V = O.etd2rkds_step(U, V, p, mats)
+    dt = time.perf_counter() - t0
+    return {
+        "value": workload.N * steps / dt,
+        "unit": "grid-point-steps/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": f"{steps} ETD2RKds steps of {workload.name} (numpy FP64 oracle, "
+                  f"{dt:.1f} s, BLAS threads={threads}, host cpus={os.cpu_count()})",
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16x3"])
+    ap.add_argument("--scheme", default="etd2rkds", choices=["etd2rkds", "lawson2b"])
+    ap.add_argument("--n", type=int, default=256, help="grid side of the 3D Brusselator workload")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of this many MiB three times "
+                         "(reference traffic for hardware byte counters)")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only (the hot path is a single-GPU "
+              "kernel; sharding across GPUs is a design note, not implemented). Use --gpus 1.",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    import paper_2307_10684_amd as adr
+    import synth as S
+
+    if args.copy_calibration > 0:
+        count = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(count, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            adr.adr_device_copy(src, dst, count)
+        torch.cuda.synchronize()
+        del src, dst
+
+    w = S.brusselator_3d(args.n)
+    d, N = w.d, w.N
+    solver = adr.Solver(w, scheme=args.scheme, precision=args.precision)
+    U0, V0 = S.initial_state(w, args.seed)
+    Ud, Vd = solver.upload(U0, V0)
+    U_init, V_init = Ud.clone(), Vd.clone()
+    torch.cuda.synchronize()
+
+    # warm-up, then restart from the initial state
+    if args.warmup > 0:
+        solver.solve(Ud, Vd, args.warmup)
+    Ud.copy_(U_init)
+    Vd.copy_(V_init)
+    torch.cuda.synchronize()
+
+    # ---- timed region: exactly `steps` steps in one adr_solve call
+    t0 = time.perf_counter()
+    solver.solve(Ud, Vd, args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    finite = bool(torch.isfinite(Ud).all().item() and torch.isfinite(Vd).all().item())
+
+    # ---- same steps again with per-launch HIP events (kernel durations)
+    launches_per_step = 2 * d + 2
+    Ud.copy_(U_init)
+    Vd.copy_(V_init)
+    torch.cuda.synchronize()
+    adr.adr_timing_enable(args.steps * launches_per_step + 8)
+    t1 = time.perf_counter()
+    solver.solve(Ud, Vd, args.steps)
+    torch.cuda.synchronize()
+    elapsed_ev = time.perf_counter() - t1
+    n_mode, ms_mode = adr.adr_timing_read(0)
+    n_stage, ms_stage = adr.adr_timing_read(1)
+    adr.adr_timing_enable(0)
+
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = N * args.steps / elapsed
+    mode_avg_ms = ms_mode / max(n_mode, 1)
+    # algorithmic work of one mode-product launch: both components, 2*n_mu*N flops each
+    flops_per_launch = 2 * 2.0 * (sum(w.n) / d) * N
+    elem = {"f64": 8, "f32": 4, "bf16x3": 4}[args.precision]
+    peak = {"f64": PEAKS["f64_mfma_tflops"], "f32": PEAKS["f32_mfma_tflops"],
+            "bf16x3": PEAKS["bf16_mfma_tflops"]}[args.precision]
+    achieved = flops_per_launch / (mode_avg_ms * 1e-3) / 1e12
+    bytes_per_launch = 2 * 2 * elem * N  # read + write one tensor per component
+    traffic = _traffic_from_profiles(args.precision, w.name)
+    stage_avg_ms = ms_stage / max(n_stage, 1)
+    stage_bytes = (32 + 48) / 2 * N  # average of stage 1 (32 B/pt) and stage 2 (48 B/pt)
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": list(w.n), "scheme": args.scheme,
+                   "precision": args.precision, "tau": w.tau, "seed": args.seed,
+                   "model": "advective Brusselator (A=1, B=3, Du=1e-3, Dv=5e-3, alpha=0.1*(1,.5,.25))"},
+        "roofline": {
+            "kernel": f"mode_product_{args.precision}",
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": traffic,
+            "avg_launch_ms": mode_avg_ms,
+            "launches": n_mode,
+            "flops_per_launch": flops_per_launch,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+        },
+        "stage_kernels": {
+            "bound": "hbm",
+            "avg_launch_ms": stage_avg_ms,
+            "achieved": stage_bytes / (stage_avg_ms * 1e-3) / 1e9,
+            "peak": PEAKS["hbm_gbs"],
+            "unit": "GB/s",
+            "launches": n_stage,
+        },
+        "timing_pass_ms_per_step": 1e3 * elapsed_ev / args.steps,
+        "finite": finite,
+        "paper_context": "paper (MATLAB, i7-10750H 6 cores): 64^3 Brusselator ETD2RKds 9.1e-3 s/step "
+                         "= 2.9e7 grid-point-steps/s",
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

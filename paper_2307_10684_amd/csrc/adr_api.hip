@@ -128,7 +128,7 @@ int check_problem(const adr_problem* p, Geometry& g) {
     g.n[mu] = p->n[mu];
     g.N *= p->n[mu];
   }
-  if (g.N > (1LL << 31)) return ADR_EINVAL;
+  if (g.N >= (1LL << 31)) return ADR_EINVAL;
   for (int c = 0; c < 2; ++c)
     for (int mu = 0; mu < p->d; ++mu) {
       if (p->scheme == ADR_ETD2RKDS) {
@@ -536,7 +536,7 @@ int adr_mode_product(int d, const int32_t* n, int mu, const double* M, const dou
     g.n[k] = n[k];
     g.N *= n[k];
   }
-  if (g.N > (1LL << 31) || n[mu] > 4096) return ADR_EINVAL;
+  if (g.N >= (1LL << 31) || n[mu] > 4096) return ADR_EINVAL;
   ModeArgs a{};
   a.W[0] = W;
   a.M[0] = M;
@@ -576,7 +576,7 @@ int adr_tucker(int d, const int32_t* n, const double* const* M, const double* W,
     g.n[k] = n[k];
     g.N *= n[k];
   }
-  if (g.N > (1LL << 31)) return ADR_EINVAL;
+  if (g.N >= (1LL << 31)) return ADR_EINVAL;
   const size_t need = adr_tucker_workspace_bytes(d, n);
   if (d > 1 && (!work || work_bytes < need)) return ADR_ENOMEM;
   TuckerGroup tg;

@@ -5,9 +5,9 @@
 //
 // The tensor is viewed as (L, n, R) (see ModeArgs).  Each workgroup computes a
 // BI x BX output tile: BI rows i of the n x n matrix against BX fibres x, with
-// the contraction over k staged through LDS in chunks of BK = 16.  This is a
-// GEMM whose small operand M is shared by every workgroup (it stays in L2)
-// and whose large operand W is streamed from HBM once per i-tile.
+// the contraction over k staged through LDS in chunks of BK.  This is a GEMM
+// whose small operand M is shared by every workgroup (it stays in L2) and
+// whose large operand W is streamed from HBM once per i-tile.
 //
 // Two memory orientations:
 //  * L > 1 ("x-contiguous"): consecutive fibres are consecutive in memory, so
@@ -20,34 +20,43 @@
 // Fragment layout of v_mfma_f64_16x16x4f64 (wave64): lane l supplies
 // A[l%16][l/16] and B[l/16][l%16]; it receives D[l/16 + 4v][l%16], v = 0..3
 // (the row interleave differs from the FP32 16x16x4 instruction).
+//
+// Element indices fit in 32 bits (the host rejects tensors of 2^31 or more
+// elements), so loads use a 32-bit offset from a scalar base pointer.
 #include "common.h"
 
 namespace adr {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
-constexpr int kThreads = 256;  // 4 waves
-constexpr int kBK = 16;        // contraction chunk
-constexpr int kPad = 16;       // row padding (doubles): next k-row lands 32 banks away
-constexpr int kLdK = kBK + 2;  // k-fastest W tile row length: conflict-free fragment reads
+constexpr int kPad = 16;  // row padding (doubles): the next k-row lands 32 banks away
 
-template <int BI, int BX, int WI, int WX, bool KFAST>
-__global__ __launch_bounds__(kThreads, 2) void k_mode_f64(ModeArgs a, int n_itiles,
-                                                         int n_xtiles) {
-  static_assert(WI * WX == kThreads / 64, "four waves per workgroup");
+// FULL: every tile is complete (n % BI == 0, n % BK == 0, X % BX == 0), so the
+// loads need no bounds predicates and stay in flight across the MFMAs.
+template <int BI, int BX, int WI, int WX, int BK, bool KFAST, bool FULL, int MINB = 2>
+__global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64(ModeArgs a, int n_itiles,
+                                                                int n_xtiles) {
+  constexpr int NT = 64 * WI * WX;
   constexpr int TI = BI / WI, TX = BX / WX;  // wave tile
   constexpr int FI = TI / 16, FX = TX / 16;  // 16x16 blocks per wave
   static_assert(FI * 16 == TI && FX * 16 == TX, "wave tile must be a multiple of 16");
+  static_assert(BK % 4 == 0, "k chunk must be a multiple of the MFMA depth");
   constexpr int LDI = BI + kPad;
   constexpr int LDX = BX + kPad;
-  constexpr int SW = KFAST ? BX * kLdK : kBK * LDX;   // W tile size in LDS
-  constexpr int MROWS = kThreads / BI;                // k-rows of M loaded per pass
-  constexpr int MLOADS = kBK / MROWS;                 // passes (doubles per thread)
-  constexpr int WLOADS = BX * kBK / kThreads;         // W doubles per thread
-  static_assert(MROWS * BI == kThreads && MLOADS * MROWS == kBK, "M tile mapping");
+  constexpr int LDK = BK + 2;                          // k-fastest rows: conflict-free fragments
+  constexpr int SW = KFAST ? BX * LDK : BK * LDX;      // W tile size in LDS
+  constexpr int MROWS = NT / BI;                       // k-rows of M loaded per pass
+  constexpr int MLOADS = BK / MROWS;                   // doubles per thread
+  static_assert(MROWS * BI == NT && MLOADS * MROWS == BK, "M tile mapping");
+  constexpr int WROWS = NT / BX;                       // x-contiguous: k-rows per pass
+  constexpr int XSTEP = NT / BK;                       // k-contiguous: fibres per pass
+  constexpr int WLOADS = BX * BK / NT;                 // W doubles per thread
+  static_assert(KFAST ? (XSTEP * BK == NT && WLOADS * XSTEP == BX)
+                      : (WROWS * BX == NT && WLOADS * WROWS == BK), "W tile mapping");
 
-  __shared__ double sM[2][kBK * LDI];
+  __shared__ double sM[2][BK * LDI];
   __shared__ double sW[2][SW];
 
   const int tid = threadIdx.x;
@@ -67,71 +76,67 @@ __global__ __launch_bounds__(kThreads, 2) void k_mode_f64(ModeArgs a, int n_itil
   const int g = t / n_xtiles;
 
   const int n = a.n;
-  const long long L = a.L, X = a.X;
-  const long long Ln = L * (long long)n;
+  const unsigned L = (unsigned)a.L;
+  const unsigned X = (unsigned)a.X;
+  const unsigned Ln = L * (unsigned)n;
   const int i0 = itile * BI;
-  const long long x0 = (long long)xtile * BX;
+  const unsigned x0 = (unsigned)xtile * BX;
   const double* __restrict__ W = static_cast<const double*>(a.W[g]);
   const double* __restrict__ M = static_cast<const double*>(a.M[g]);
 
   // ---- per-thread load descriptors ------------------------------------------
-  const int m_i = tid % BI;          // M: row i0 + m_i, k-rows m_k0 + p*MROWS
+  const int m_i = tid % BI;  // M: row i0 + m_i, k-rows m_k0 + p*MROWS
   const int m_k0 = tid / BI;
   const bool m_iok = (i0 + m_i) < n;
+  const unsigned m_base = (unsigned)(i0 + m_i) + (unsigned)n * (unsigned)m_k0;
 
-  // x-contiguous W: fibre x0 + w_x, k-rows w_k0 + p*(kThreads/BX)
-  // k-contiguous W: k-row w_k, fibres w_x0 + p*(kThreads/kBK)
-  long long w_off = -1;
-  int w_a = 0, w_b = 0;
+  int w_a, w_b;
+  unsigned w_base = 0;
+  bool w_ok = true;
   if (!KFAST) {
-    w_a = tid % BX;          // x within tile
-    w_b = tid / BX;          // first k-row
-    const long long x = x0 + w_a;
-    if (x < X) {
-      const long long l = x % L, r = x / L;
-      w_off = l + Ln * r;
-    }
+    w_a = tid % BX;  // x within tile
+    w_b = tid / BX;  // first k-row
+    const unsigned x = x0 + w_a;
+    w_ok = x < X;
+    if (w_ok) w_base = (x % L) + Ln * (x / L) + L * (unsigned)w_b;
   } else {
-    w_a = tid % kBK;         // k within chunk
-    w_b = tid / kBK;         // first fibre within tile
+    w_a = tid % BK;  // k within chunk
+    w_b = tid / BK;  // first fibre within tile
+    w_base = (x0 + w_b) * (unsigned)n + (unsigned)w_a;
   }
 
   double rm[MLOADS], rw[WLOADS];
 
+  // Loads read raw values (out-of-range elements read index 0); the zeroing of
+  // out-of-range elements happens when the chunk is written to LDS, after the
+  // MFMAs of the current chunk, so the loads stay in flight during the compute.
+  auto m_ok = [&](int k0, int p) { return FULL || (m_iok && (k0 + m_k0 + p * MROWS) < n); };
+  auto w_okp = [&](int k0, int p) {
+    return FULL || (KFAST ? ((k0 + w_a) < n && (x0 + w_b + p * XSTEP) < X)
+                          : (w_ok && (k0 + w_b + p * WROWS) < n));
+  };
   auto load_chunk = [&](int k0) {
 #pragma unroll
-    for (int p = 0; p < MLOADS; ++p) {
-      const int k = k0 + m_k0 + p * MROWS;
-      rm[p] = (m_iok && k < n) ? M[(i0 + m_i) + (long long)n * k] : 0.0;
-    }
-    if (!KFAST) {
-      constexpr int WROWS = kThreads / BX;
+    for (int p = 0; p < MLOADS; ++p)
+      rm[p] = M[m_ok(k0, p) ? m_base + (unsigned)n * (unsigned)(k0 + p * MROWS) : 0u];
 #pragma unroll
-      for (int p = 0; p < WLOADS; ++p) {
-        const int k = k0 + w_b + p * WROWS;
-        rw[p] = (w_off >= 0 && k < n) ? W[w_off + L * k] : 0.0;
-      }
-    } else {
-      constexpr int XSTEP = kThreads / kBK;
-      const int k = k0 + w_a;
-#pragma unroll
-      for (int p = 0; p < WLOADS; ++p) {
-        const long long x = x0 + w_b + p * XSTEP;
-        rw[p] = (x < X && k < n) ? W[x * n + k] : 0.0;
-      }
+    for (int p = 0; p < WLOADS; ++p) {
+      const unsigned off = KFAST ? (unsigned)n * (unsigned)(p * XSTEP) + (unsigned)k0
+                                 : L * (unsigned)(k0 + p * WROWS);
+      rw[p] = W[w_okp(k0, p) ? w_base + off : 0u];
     }
   };
-  auto store_chunk = [&](int buf) {
+  auto store_chunk = [&](int buf, int k0) {
 #pragma unroll
-    for (int p = 0; p < MLOADS; ++p) sM[buf][(m_k0 + p * MROWS) * LDI + m_i] = rm[p];
-    if (!KFAST) {
-      constexpr int WROWS = kThreads / BX;
+    for (int p = 0; p < MLOADS; ++p)
+      sM[buf][(m_k0 + p * MROWS) * LDI + m_i] = m_ok(k0, p) ? rm[p] : 0.0;
 #pragma unroll
-      for (int p = 0; p < WLOADS; ++p) sW[buf][(w_b + p * WROWS) * LDX + w_a] = rw[p];
-    } else {
-      constexpr int XSTEP = kThreads / kBK;
-#pragma unroll
-      for (int p = 0; p < WLOADS; ++p) sW[buf][(w_b + p * XSTEP) * kLdK + w_a] = rw[p];
+    for (int p = 0; p < WLOADS; ++p) {
+      const double v = w_okp(k0, p) ? rw[p] : 0.0;
+      if (!KFAST)
+        sW[buf][(w_b + p * WROWS) * LDX + w_a] = v;
+      else
+        sW[buf][(w_b + p * XSTEP) * LDK + w_a] = v;
     }
   };
 
@@ -141,20 +146,20 @@ __global__ __launch_bounds__(kThreads, 2) void k_mode_f64(ModeArgs a, int n_itil
 #pragma unroll
     for (int fx = 0; fx < FX; ++fx) acc[fi][fx] = d4{0.0, 0.0, 0.0, 0.0};
 
-  const int nchunks = (n + kBK - 1) / kBK;
+  const int nchunks = (n + BK - 1) / BK;
   load_chunk(0);
-  store_chunk(0);
+  store_chunk(0, 0);
   __syncthreads();
 
   const int col = lane & 15;
   const int krow = lane >> 4;
   for (int c = 0; c < nchunks; ++c) {
     const int buf = c & 1;
-    if (c + 1 < nchunks) load_chunk((c + 1) * kBK);
+    if (c + 1 < nchunks) load_chunk((c + 1) * BK);
     const double* sm = sM[buf];
     const double* sw = sW[buf];
 #pragma unroll
-    for (int kk = 0; kk < kBK; kk += 4) {
+    for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + krow;
       double af[FI], bf[FX];
 #pragma unroll
@@ -162,7 +167,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_mode_f64(ModeArgs a, int n_itil
 #pragma unroll
       for (int fx = 0; fx < FX; ++fx) {
         const int xl = wx * TX + fx * 16 + col;
-        bf[fx] = KFAST ? sw[xl * kLdK + kr] : sw[kr * LDX + xl];
+        bf[fx] = KFAST ? sw[xl * LDK + kr] : sw[kr * LDX + xl];
       }
 #pragma unroll
       for (int fi = 0; fi < FI; ++fi)
@@ -171,7 +176,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_mode_f64(ModeArgs a, int n_itil
           acc[fi][fx] = KFAST ? __builtin_amdgcn_mfma_f64_16x16x4f64(bf[fx], af[fi], acc[fi][fx], 0, 0, 0)
                               : __builtin_amdgcn_mfma_f64_16x16x4f64(af[fi], bf[fx], acc[fi][fx], 0, 0, 0);
     }
-    if (c + 1 < nchunks) store_chunk(buf ^ 1);
+    if (c + 1 < nchunks) store_chunk(buf ^ 1, (c + 1) * BK);
     __syncthreads();
   }
 
@@ -184,16 +189,16 @@ __global__ __launch_bounds__(kThreads, 2) void k_mode_f64(ModeArgs a, int n_itil
   if (!KFAST) {
 #pragma unroll
     for (int fx = 0; fx < FX; ++fx) {
-      const long long x = x0 + wx * TX + fx * 16 + col;
+      const unsigned x = x0 + wx * TX + fx * 16 + col;
       if (x >= X) continue;
-      const long long xo = (x % L) + Ln * (x / L);
+      const unsigned xo = (x % L) + Ln * (x / L);
 #pragma unroll
       for (int fi = 0; fi < FI; ++fi) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = i0 + wi * TI + fi * 16 + krow + 4 * v;
           if (i < n) {
-            const long long o = xo + L * i;
+            const unsigned o = xo + L * (unsigned)i;
             double val = alpha * acc[fi][fx][v];
             if (Y) val += beta * Y[o];
             if (Z) val += gamma * Z[o];
@@ -211,9 +216,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_mode_f64(ModeArgs a, int n_itil
       for (int fx = 0; fx < FX; ++fx) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const long long x = x0 + wx * TX + fx * 16 + krow + 4 * v;
+          const unsigned x = x0 + wx * TX + fx * 16 + krow + 4 * v;
           if (x < X) {
-            const long long o = x * n + i;
+            const unsigned o = x * (unsigned)n + (unsigned)i;
             double val = alpha * acc[fi][fx][v];
             if (Y) val += beta * Y[o];
             if (Z) val += gamma * Z[o];
@@ -225,26 +230,295 @@ __global__ __launch_bounds__(kThreads, 2) void k_mode_f64(ModeArgs a, int n_itil
   }
 }
 
-template <int BI, int BX, int WI, int WX>
+// Persistent variant for evenly tiled shapes (n % BI == 0, X % BX == 0,
+// 16-byte aligned rows): a grid of about two workgroups per CU walks the tiles,
+// loads move two doubles per lane, and the first k-chunk of the next tile is
+// fetched while the last chunk of the current one is multiplied, so tile
+// boundaries (epilogue stores, first loads) overlap with MFMA work.
+template <int BI, int BX, int WI, int WX, int BK, bool KFAST>
+__global__ __launch_bounds__(64 * WI * WX, 2) void k_mode_f64_persist(ModeArgs a, int n_itiles,
+                                                                     int n_xtiles, int ntiles) {
+  constexpr int NT = 64 * WI * WX;
+  constexpr int TI = BI / WI, TX = BX / WX;
+  constexpr int FI = TI / 16, FX = TX / 16;
+  static_assert(FI * 16 == TI && FX * 16 == TX, "wave tile must be a multiple of 16");
+  constexpr int LDI = BI + kPad;
+  constexpr int LDX = BX + kPad;
+  constexpr int LDK = BK + 2;
+  constexpr int SW = KFAST ? BX * LDK : BK * LDX;
+  // pair-granular load mappings (each lane moves two consecutive doubles)
+  constexpr int MPR = BI / 2;            // lanes per M k-row
+  constexpr int MROWS = NT / MPR;        // k-rows per pass
+  constexpr int MLOADS = BK / MROWS;     // passes
+  static_assert(MROWS * MPR == NT && MLOADS * MROWS == BK, "M mapping");
+  constexpr int WPR = BX / 2;            // x-contiguous: lanes per k-row
+  constexpr int WROWS = NT / WPR;
+  constexpr int KPR = BK / 2;            // k-contiguous: lanes per fibre
+  constexpr int XSTEP = NT / KPR;        // fibres per pass
+  constexpr int WLOADS = KFAST ? BX / XSTEP : BK / WROWS;
+  static_assert(KFAST ? (XSTEP * KPR == NT && WLOADS * XSTEP == BX)
+                      : (WROWS * WPR == NT && WLOADS * WROWS == BK), "W mapping");
+
+  __shared__ double sM[2][BK * LDI];
+  __shared__ double sW[2][SW];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wi = wave / WX, wx = wave % WX;
+  const int col = lane & 15;
+  const int krow = lane >> 4;
+
+  const int n = a.n;
+  const unsigned L = (unsigned)a.L;
+  const unsigned Ln = L * (unsigned)n;
+  const int nchunks = n / BK;
+
+  // tile sequence of this workgroup: XCD-contiguous ranges (see k_mode_f64)
+  const int G = gridDim.x;
+  const int b = blockIdx.x;
+  const int per = (ntiles + G - 1) / G;     // tiles per workgroup (upper bound)
+  // workgroup b handles logical tiles base, base+1, ... within its XCD's range
+  const int xcd = b % 8, slot = b / 8, slots = (G + 7) / 8;
+  (void)slots;
+
+  // per-tile state; the group member's pointers are picked with explicit selects
+  // (a dynamic index into the kernel-argument arrays would spill them to scratch)
+  struct TileDesc {
+    int g, i0;
+    unsigned x0;
+    const double* W;
+    const double* M;
+  };
+  auto pick = [](const void* const* arr, int g) {
+    const void* p = arr[0];
+    p = g == 1 ? arr[1] : p;
+    p = g == 2 ? arr[2] : p;
+    p = g == 3 ? arr[3] : p;
+    return p;
+  };
+  auto tile_of = [&](int t) {
+    TileDesc d;
+    const int itile = t % n_itiles;
+    const int rest = t / n_itiles;
+    d.i0 = itile * BI;
+    d.x0 = (unsigned)(rest % n_xtiles) * BX;
+    d.g = rest / n_xtiles;
+    d.W = static_cast<const double*>(pick(a.W, d.g));
+    d.M = static_cast<const double*>(pick(a.M, d.g));
+    return d;
+  };
+  // logical tile k of this workgroup (k = 0, 1, ...); -1 when done
+  auto tile_index = [&](int k) {
+    const int t = (G % 8 == 0) ? xcd * (G / 8) * per + slot * per + k : b * per + k;
+    return (k < per && t < ntiles) ? t : -1;
+  };
+
+  const int m_j = tid % MPR, m_k0 = tid / MPR;
+  const int w_j = KFAST ? tid % KPR : tid % WPR;
+  const int w_b = KFAST ? tid / KPR : tid / WPR;
+
+  d2 rm[MLOADS], rw[WLOADS];
+  auto load_chunk = [&](const double* __restrict__ M, const double* __restrict__ W, int i0,
+                        unsigned x0, int k0) {
+#pragma unroll
+    for (int p = 0; p < MLOADS; ++p) {
+      const unsigned idx = (unsigned)(i0 + 2 * m_j) + (unsigned)n * (unsigned)(k0 + m_k0 + p * MROWS);
+      rm[p] = *reinterpret_cast<const d2*>(M + idx);
+    }
+    if (!KFAST) {
+      const unsigned x = x0 + 2 * w_j;
+      const unsigned base = (x % L) + Ln * (x / L);
+#pragma unroll
+      for (int p = 0; p < WLOADS; ++p)
+        rw[p] = *reinterpret_cast<const d2*>(W + base + L * (unsigned)(k0 + w_b + p * WROWS));
+    } else {
+#pragma unroll
+      for (int p = 0; p < WLOADS; ++p) {
+        const unsigned x = x0 + w_b + p * XSTEP;
+        rw[p] = *reinterpret_cast<const d2*>(W + x * (unsigned)n + (unsigned)(k0 + 2 * w_j));
+      }
+    }
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < MLOADS; ++p)
+      *reinterpret_cast<d2*>(&sM[buf][(m_k0 + p * MROWS) * LDI + 2 * m_j]) = rm[p];
+#pragma unroll
+    for (int p = 0; p < WLOADS; ++p) {
+      if (!KFAST)
+        *reinterpret_cast<d2*>(&sW[buf][(w_b + p * WROWS) * LDX + 2 * w_j]) = rw[p];
+      else
+        *reinterpret_cast<d2*>(&sW[buf][(w_b + p * XSTEP) * LDK + 2 * w_j]) = rw[p];
+    }
+  };
+
+  int k = 0;
+  int t = tile_index(0);
+  if (t < 0) return;
+  TileDesc cur = tile_of(t);
+  load_chunk(cur.M, cur.W, cur.i0, cur.x0, 0);
+  store_chunk(0);
+  __syncthreads();
+  int buf = 0;
+
+  const double alpha = a.alpha, beta = a.beta, gamma = a.gamma;
+  while (true) {
+    const int tn = tile_index(k + 1);
+    const TileDesc nxt = tile_of(tn < 0 ? 0 : tn);
+    d4 acc[FI][FX];
+#pragma unroll
+    for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+      for (int fx = 0; fx < FX; ++fx) acc[fi][fx] = d4{0.0, 0.0, 0.0, 0.0};
+
+    for (int c = 0; c < nchunks; ++c) {
+      // next chunk: the following one of this tile, or the first of the next tile
+      const bool in_tile = c + 1 < nchunks;
+      const bool more = in_tile || tn >= 0;
+      if (more) {
+        const double* Mn = in_tile ? cur.M : nxt.M;
+        const double* Wn = in_tile ? cur.W : nxt.W;
+        const int i0n = in_tile ? cur.i0 : nxt.i0;
+        const unsigned x0n = in_tile ? cur.x0 : nxt.x0;
+        load_chunk(Mn, Wn, i0n, x0n, in_tile ? (c + 1) * BK : 0);
+      }
+      const double* sm = sM[buf];
+      const double* sw = sW[buf];
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        const int kr = kk + krow;
+        double af[FI], bf[FX];
+#pragma unroll
+        for (int fi = 0; fi < FI; ++fi) af[fi] = sm[kr * LDI + wi * TI + fi * 16 + col];
+#pragma unroll
+        for (int fx = 0; fx < FX; ++fx) {
+          const int xl = wx * TX + fx * 16 + col;
+          bf[fx] = KFAST ? sw[xl * LDK + kr] : sw[kr * LDX + xl];
+        }
+#pragma unroll
+        for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+          for (int fx = 0; fx < FX; ++fx)
+            acc[fi][fx] = KFAST ? __builtin_amdgcn_mfma_f64_16x16x4f64(bf[fx], af[fi], acc[fi][fx], 0, 0, 0)
+                                : __builtin_amdgcn_mfma_f64_16x16x4f64(af[fi], bf[fx], acc[fi][fx], 0, 0, 0);
+      }
+      if (more) store_chunk(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+
+    // epilogue of the current tile (the next tile's first chunk is already in LDS)
+    double* out = static_cast<double*>(const_cast<void*>(pick(a.out, cur.g)));
+    const double* Y = static_cast<const double*>(pick(reinterpret_cast<const void* const*>(a.Y), cur.g));
+    const double* Z = static_cast<const double*>(pick(reinterpret_cast<const void* const*>(a.Z), cur.g));
+    if (!KFAST) {
+#pragma unroll
+      for (int fx = 0; fx < FX; ++fx) {
+        const unsigned x = cur.x0 + wx * TX + fx * 16 + col;
+        const unsigned xo = (x % L) + Ln * (x / L);
+#pragma unroll
+        for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const unsigned o = xo + L * (unsigned)(cur.i0 + wi * TI + fi * 16 + krow + 4 * v);
+            double val = alpha * acc[fi][fx][v];
+            if (Y) val += beta * Y[o];
+            if (Z) val += gamma * Z[o];
+            out[o] = val;
+          }
+      }
+    } else {
+#pragma unroll
+      for (int fi = 0; fi < FI; ++fi) {
+        const unsigned i = (unsigned)(cur.i0 + wi * TI + fi * 16 + col);
+#pragma unroll
+        for (int fx = 0; fx < FX; ++fx)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const unsigned x = cur.x0 + wx * TX + fx * 16 + krow + 4 * v;
+            const unsigned o = x * (unsigned)n + i;
+            double val = alpha * acc[fi][fx][v];
+            if (Y) val += beta * Y[o];
+            if (Z) val += gamma * Z[o];
+            out[o] = val;
+          }
+      }
+    }
+    if (tn < 0) break;
+    cur = nxt;
+    ++k;
+  }
+}
+
+int device_cu_count() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+  }
+  return cus;
+}
+
+template <int BI, int BX, int WI, int WX, int BK>
+bool launch_persist(const ModeArgs& a, hipStream_t s, hipError_t& err) {
+  // evenly tiled, pair-aligned shapes only
+  if (a.n % BI != 0 || a.n % BK != 0 || a.X % BX != 0) return false;
+  if (a.L != 1 && a.L % 2 != 0) return false;
+  if (a.n % 2 != 0) return false;
+  for (int g = 0; g < a.group; ++g)
+    if ((reinterpret_cast<uintptr_t>(a.W[g]) | reinterpret_cast<uintptr_t>(a.M[g])) % 16 != 0)
+      return false;
+  const int n_itiles = a.n / BI;
+  const long long n_xtiles = a.X / BX;
+  const long long ntiles = (long long)a.group * n_itiles * n_xtiles;
+  if (ntiles <= 0 || ntiles > 0x7fffffffLL || a.X >= (1LL << 31)) return false;
+  long long grid = 2LL * device_cu_count();
+  if (grid > ntiles) grid = ntiles;
+  constexpr int NT = 64 * WI * WX;
+  if (a.L == 1)
+    hipLaunchKernelGGL((k_mode_f64_persist<BI, BX, WI, WX, BK, true>), dim3((unsigned)grid),
+                       dim3(NT), 0, s, a, n_itiles, (int)n_xtiles, (int)ntiles);
+  else
+    hipLaunchKernelGGL((k_mode_f64_persist<BI, BX, WI, WX, BK, false>), dim3((unsigned)grid),
+                       dim3(NT), 0, s, a, n_itiles, (int)n_xtiles, (int)ntiles);
+  err = hipGetLastError();
+  return true;
+}
+
+template <int BI, int BX, int WI, int WX, int BK, int MINB = 2>
 hipError_t launch_cfg(const ModeArgs& a, hipStream_t s) {
   const int n_itiles = (a.n + BI - 1) / BI;
   const long long n_xtiles = (a.X + BX - 1) / BX;
   const long long grid = (long long)a.group * n_itiles * n_xtiles;
-  if (grid <= 0 || grid > 0x7fffffffLL || n_xtiles > 0x7fffffffLL) return hipErrorInvalidValue;
-  if (a.L == 1)
-    hipLaunchKernelGGL((k_mode_f64<BI, BX, WI, WX, true>), dim3((unsigned)grid), dim3(kThreads), 0,
-                       s, a, n_itiles, (int)n_xtiles);
-  else
-    hipLaunchKernelGGL((k_mode_f64<BI, BX, WI, WX, false>), dim3((unsigned)grid), dim3(kThreads), 0,
-                       s, a, n_itiles, (int)n_xtiles);
+  if (grid <= 0 || grid > 0x7fffffffLL || a.X >= (1LL << 31)) return hipErrorInvalidValue;
+  constexpr int NT = 64 * WI * WX;
+  const bool full = (a.n % BI == 0) && (a.n % BK == 0) && (a.X % BX == 0);
+  const dim3 gd((unsigned)grid), bd(NT);
+  const int nx = (int)n_xtiles;
+  if (a.L == 1) {
+    if (full) hipLaunchKernelGGL((k_mode_f64<BI, BX, WI, WX, BK, true, true, MINB>), gd, bd, 0, s, a, n_itiles, nx);
+    else hipLaunchKernelGGL((k_mode_f64<BI, BX, WI, WX, BK, true, false, MINB>), gd, bd, 0, s, a, n_itiles, nx);
+  } else {
+    if (full) hipLaunchKernelGGL((k_mode_f64<BI, BX, WI, WX, BK, false, true, MINB>), gd, bd, 0, s, a, n_itiles, nx);
+    else hipLaunchKernelGGL((k_mode_f64<BI, BX, WI, WX, BK, false, false, MINB>), gd, bd, 0, s, a, n_itiles, nx);
+  }
   return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_mode_product_f64(const ModeArgs& a, hipStream_t s) {
-  if (a.n <= 64) return launch_cfg<64, 128, 1, 4>(a, s);
-  return launch_cfg<128, 128, 2, 2>(a, s);
+  hipError_t e = hipSuccess;
+  if (a.n <= 64) {
+    if (launch_persist<64, 128, 1, 4, 16>(a, s, e)) return e;
+    return launch_cfg<64, 128, 1, 4, 16>(a, s);
+  }
+  if (launch_persist<128, 128, 2, 2, 16>(a, s, e)) return e;
+  return launch_cfg<128, 128, 2, 2, 16>(a, s);
 }
 
 }  // namespace adr

@@ -41,74 +41,97 @@ __device__ __forceinline__ void put(void* p, long long q, double x) {
 
 // Stage 1: R^c = sum_mu (C x_mu A_mu^c) + G^c(U, V) for the directions with a
 // band; directions without one are added afterwards by dense mode products.
-// Block = (64, 4): each wave covers 64 consecutive i_1 of one grid row, so the
-// i_1 +- 1 neighbours come from lane shuffles; i_2, i_3 neighbours are plain
-// loads that hit in cache (the rows were just streamed by nearby waves).
+// Block = (64, 4) threads over (i_1, i_2); each block marches through ZB planes
+// of i_3.  The loop is software-pipelined: while plane z is computed, the
+// values of plane z+1 that a thread needs (its own point, its i_2 +- 1
+// neighbours and, on the wave edges, its i_1 +- 1 neighbours) are already in
+// flight, and the i_3 neighbours are the previous / next planes held in
+// registers.  Inside a wave the i_1 +- 1 neighbours come from lane shuffles.
+constexpr int kZB = 16;  // planes per block
+
+struct Plane {
+  double c, ym, yp, xm, xp;  // centre, i_2 -+ 1, i_1 -+ 1 (wave-edge lanes only)
+};
+
 template <typename TR>
 __global__ __launch_bounds__(256) void k_etd_stage1(StageGeom g, Reaction r,
                                                     const double* __restrict__ U,
                                                     const double* __restrict__ V, void* Ru,
-                                                    void* Rv, long long rows) {
-  const int n1 = g.n[0];
+                                                    void* Rv) {
+  const int n1 = g.n[0], n2 = g.d >= 2 ? g.n[1] : 1, n3 = g.d >= 3 ? g.n[2] : 1;
   const int i1 = blockIdx.x * 64 + threadIdx.x;
-  for (long long row = (long long)blockIdx.y * 4 + threadIdx.y; row < rows;
-       row += (long long)gridDim.y * 4) {
-    const bool live = i1 < n1;
-    const long long q = row * n1 + i1;
-    const double u = live ? U[q] : 0.0;
-    const double v = live ? V[q] : 0.0;
-    // i_1 neighbours from the adjacent lanes; the wave edges load directly
-    double um = __shfl_up(u, 1, 64), up = __shfl_down(u, 1, 64);
-    double vm = __shfl_up(v, 1, 64), vp = __shfl_down(v, 1, 64);
-    const int lane = threadIdx.x;
-    if (lane == 0) {
-      um = (live && i1 > 0) ? U[q - 1] : 0.0;
-      vm = (live && i1 > 0) ? V[q - 1] : 0.0;
+  const int i2 = blockIdx.y * 4 + threadIdx.y;
+  const int z0 = blockIdx.z * kZB;
+  const int z1 = min(z0 + kZB, n3);
+  const bool live = i1 < n1 && i2 < n2;
+  const unsigned P = (unsigned)n1 * (unsigned)n2;  // plane stride
+  const int lane = threadIdx.x;
+  // per-thread band coefficients of directions 1 and 2 (zero where there is no
+  // neighbour and where the direction has no band)
+  double a1u[3] = {0, 0, 0}, a1v[3] = {0, 0, 0}, a2u[3] = {0, 0, 0}, a2v[3] = {0, 0, 0};
+  if (live) {
+    if (g.band[0][0]) for (int j = 0; j < 3; ++j) a1u[j] = g.band[0][0][j * n1 + i1];
+    if (g.band[1][0]) for (int j = 0; j < 3; ++j) a1v[j] = g.band[1][0][j * n1 + i1];
+    if (g.d >= 2) {
+      if (g.band[0][1]) for (int j = 0; j < 3; ++j) a2u[j] = g.band[0][1][j * n2 + i2];
+      if (g.band[1][1]) for (int j = 0; j < 3; ++j) a2v[j] = g.band[1][1][j * n2 + i2];
     }
-    if (lane == 63 || i1 + 1 >= n1) {
-      up = (live && i1 + 1 < n1) ? U[q + 1] : 0.0;
-      vp = (live && i1 + 1 < n1) ? V[q + 1] : 0.0;
+  }
+  const double* b3u = g.d >= 3 ? g.band[0][2] : nullptr;
+  const double* b3v = g.d >= 3 ? g.band[1][2] : nullptr;
+  const bool has_m2 = live && i2 > 0, has_p2 = live && i2 + 1 < n2;
+  const bool edge_m = live && lane == 0 && i1 > 0;
+  const bool edge_p = live && lane == 63 && i1 + 1 < n1;
+  const unsigned q0 = (unsigned)i2 * (unsigned)n1 + (unsigned)i1;
+
+  auto fetch = [&](const double* __restrict__ C, int z, Plane& o) {
+    const unsigned q = q0 + (unsigned)z * P;
+    o.c = live ? C[q] : 0.0;
+    o.ym = has_m2 ? C[q - n1] : 0.0;
+    o.yp = has_p2 ? C[q + n1] : 0.0;
+    o.xm = edge_m ? C[q - 1] : 0.0;
+    o.xp = edge_p ? C[q + 1] : 0.0;
+  };
+
+  Plane cu, cv, nu, nv;
+  double pu = 0.0, pv = 0.0;  // plane z-1 centre values
+  if (live && z0 > 0) {
+    pu = U[q0 + (unsigned)(z0 - 1) * P];
+    pv = V[q0 + (unsigned)(z0 - 1) * P];
+  }
+  fetch(U, z0, cu);
+  fetch(V, z0, cv);
+  for (int z = z0; z < z1; ++z) {
+    const bool has_n3 = z + 1 < n3;
+    if (has_n3) {
+      fetch(U, z + 1, nu);
+      fetch(V, z + 1, nv);
+    } else {
+      nu = Plane{0, 0, 0, 0, 0};
+      nv = Plane{0, 0, 0, 0, 0};
     }
-    if (!live) continue;
-    if (i1 == 0) { um = 0.0; vm = 0.0; }
-    double gu, gv;
-    react(r, u, v, gu, gv);
-    double ku = 0.0, kv = 0.0;
-    // direction 1
-    if (g.band[0][0]) {
-      const double* b = g.band[0][0];
-      ku += b[i1] * um + b[n1 + i1] * u + b[2 * n1 + i1] * up;
+    // i_1 neighbours from the adjacent lanes (the edge lanes use their loads)
+    double um = __shfl_up(cu.c, 1, 64), uq = __shfl_down(cu.c, 1, 64);
+    double vm = __shfl_up(cv.c, 1, 64), vq = __shfl_down(cv.c, 1, 64);
+    if (lane == 0) { um = cu.xm; vm = cv.xm; }
+    if (lane == 63) { uq = cu.xp; vq = cv.xp; }
+    if (live) {
+      double gu, gv;
+      react(r, cu.c, cv.c, gu, gv);
+      double ku = a1u[0] * um + a1u[1] * cu.c + a1u[2] * uq;
+      double kv = a1v[0] * vm + a1v[1] * cv.c + a1v[2] * vq;
+      ku += a2u[0] * cu.ym + a2u[1] * cu.c + a2u[2] * cu.yp;
+      kv += a2v[0] * cv.ym + a2v[1] * cv.c + a2v[2] * cv.yp;
+      if (b3u) ku += b3u[z] * pu + b3u[n3 + z] * cu.c + b3u[2 * n3 + z] * nu.c;
+      if (b3v) kv += b3v[z] * pv + b3v[n3 + z] * cv.c + b3v[2 * n3 + z] * nv.c;
+      const unsigned q = q0 + (unsigned)z * P;
+      put<TR>(Ru, q, ku + gu);
+      put<TR>(Rv, q, kv + gv);
     }
-    if (g.band[1][0]) {
-      const double* b = g.band[1][0];
-      kv += b[i1] * vm + b[n1 + i1] * v + b[2 * n1 + i1] * vp;
-    }
-    // directions 2 and 3
-    long long stride = n1;
-    long long rem = row;
-#pragma unroll
-    for (int mu = 1; mu < 3; ++mu) {
-      if (mu >= g.d) break;
-      const int nm = g.n[mu];
-      const int im = (int)(rem % nm);
-      rem /= nm;
-      const bool has_m = im > 0, has_p = im + 1 < nm;
-      if (g.band[0][mu]) {
-        const double* b = g.band[0][mu];
-        const double cm = has_m ? U[q - stride] : 0.0;
-        const double cp = has_p ? U[q + stride] : 0.0;
-        ku += b[im] * cm + b[nm + im] * u + b[2 * nm + im] * cp;
-      }
-      if (g.band[1][mu]) {
-        const double* b = g.band[1][mu];
-        const double cm = has_m ? V[q - stride] : 0.0;
-        const double cp = has_p ? V[q + stride] : 0.0;
-        kv += b[im] * cm + b[nm + im] * v + b[2 * nm + im] * cp;
-      }
-      stride *= nm;
-    }
-    put<TR>(Ru, q, ku + gu);
-    put<TR>(Rv, q, kv + gv);
+    pu = cu.c;
+    pv = cv.c;
+    cu = nu;
+    cv = nv;
   }
 }
 
@@ -189,16 +212,15 @@ unsigned stream_grid(long long N) {
 
 hipError_t launch_etd_stage1(const StageGeom& g, const Reaction& r, const double* U,
                              const double* V, void* Ru, void* Rv, int r_f32, hipStream_t s) {
-  long long rows = 1;
-  for (int mu = 1; mu < g.d; ++mu) rows *= g.n[mu];
-  const unsigned gx = (unsigned)((g.n[0] + 63) / 64);
-  long long gy = (rows + 3) / 4;
-  if (gy > 65535) gy = 65535;
-  dim3 grid(gx, (unsigned)gy), block(64, 4);
+  const int n2 = g.d >= 2 ? g.n[1] : 1, n3 = g.d >= 3 ? g.n[2] : 1;
+  const dim3 grid((unsigned)((g.n[0] + 63) / 64), (unsigned)((n2 + 3) / 4),
+                  (unsigned)((n3 + kZB - 1) / kZB));
+  if (grid.y > 65535 || grid.z > 65535) return hipErrorInvalidValue;
+  const dim3 block(64, 4);
   if (r_f32)
-    hipLaunchKernelGGL(k_etd_stage1<float>, grid, block, 0, s, g, r, U, V, Ru, Rv, rows);
+    hipLaunchKernelGGL(k_etd_stage1<float>, grid, block, 0, s, g, r, U, V, Ru, Rv);
   else
-    hipLaunchKernelGGL(k_etd_stage1<double>, grid, block, 0, s, g, r, U, V, Ru, Rv, rows);
+    hipLaunchKernelGGL(k_etd_stage1<double>, grid, block, 0, s, g, r, U, V, Ru, Rv);
   return hipGetLastError();
 }
 
