@@ -63,45 +63,65 @@ bool mode_geometry(const Geometry& g, int mu, long long& L, long long& R) {
 struct TuckerGroup {
   int count = 0;
   const void* in[kMaxGroup] = {};
-  const double* M[kMaxGroup][3] = {};
+  const double* M[kMaxGroup][3] = {};      // FP64 matrices, or FP32 copies (reduced precision)
+  const unsigned short* Mh[kMaxGroup][3] = {};  // split-BF16 parts (BF16X3)
+  const unsigned short* Ml[kMaxGroup][3] = {};
   void* out[kMaxGroup] = {};
   const double* Y[kMaxGroup] = {};
   void* t1[kMaxGroup] = {};   // ping buffer
   void* t2[kMaxGroup] = {};   // pong buffer (may be the input when it may be clobbered)
 };
 
-hipError_t launch_mode(const ModeArgs& a, int precision, int in_f32, int out_f32, hipStream_t s) {
-  if (precision == ADR_F64) return launch_mode_product_f64(a, s);
-  if (precision == ADR_F32) return launch_mode_product_f32(a, in_f32, out_f32, s);
-  return launch_mode_product_bf16x3(a, in_f32, out_f32, s);
-}
-
 // out = alpha * Tucker(in; M_1..M_d) + beta * Y for every tensor of the group, applied
-// mu = 1..d.  In reduced precision the intermediates are FP32 and the last
-// product writes FP64.
+// mu = 1..d.  FP64 uses the general mode product on the natural layout.  The
+// reduced precisions chain transposing products (each reads contiguous fibres
+// and writes the next direction's fibres contiguous); their intermediates are
+// FP32 and the last product writes the FP64 result in the natural layout.
 hipError_t run_tucker(const Geometry& g, const TuckerGroup& tg, double alpha, double beta,
                       int precision, hipStream_t s) {
-  const bool lowp = precision != ADR_F64;
   for (int mu = 0; mu < g.d; ++mu) {
-    ModeArgs a{};
     const bool last = (mu == g.d - 1);
+    const void* W[kMaxGroup];
+    void* out[kMaxGroup];
     for (int k = 0; k < tg.count; ++k) {
-      a.W[k] = (mu == 0) ? tg.in[k] : ((mu % 2 == 1) ? tg.t1[k] : tg.t2[k]);
-      a.out[k] = last ? tg.out[k] : ((mu % 2 == 0) ? tg.t1[k] : tg.t2[k]);
-      a.M[k] = tg.M[k][mu];
-      a.Y[k] = last ? tg.Y[k] : nullptr;
-      a.Z[k] = nullptr;
+      W[k] = (mu == 0) ? tg.in[k] : ((mu % 2 == 1) ? tg.t1[k] : tg.t2[k]);
+      out[k] = last ? tg.out[k] : ((mu % 2 == 0) ? tg.t1[k] : tg.t2[k]);
     }
-    a.alpha = last ? alpha : 1.0;
-    a.beta = last ? beta : 0.0;
-    a.gamma = 0.0;
-    mode_geometry(g, mu, a.L, a.R);
-    a.X = a.L * a.R;
-    a.n = g.n[mu];
-    a.group = tg.count;
-    const int in_f32 = lowp ? 1 : 0;
-    const int out_f32 = (lowp && !last) ? 1 : 0;
-    hipError_t e = timed(kKindMode, s, [&] { return launch_mode(a, precision, in_f32, out_f32, s); });
+    hipError_t e;
+    if (precision == ADR_F64) {
+      ModeArgs a{};
+      for (int k = 0; k < tg.count; ++k) {
+        a.W[k] = W[k];
+        a.out[k] = out[k];
+        a.M[k] = tg.M[k][mu];
+        a.Y[k] = last ? tg.Y[k] : nullptr;
+        a.Z[k] = nullptr;
+      }
+      a.alpha = last ? alpha : 1.0;
+      a.beta = last ? beta : 0.0;
+      a.gamma = 0.0;
+      mode_geometry(g, mu, a.L, a.R);
+      a.X = a.L * a.R;
+      a.n = g.n[mu];
+      a.group = tg.count;
+      e = timed(kKindMode, s, [&] { return launch_mode_product_f64(a, s); });
+    } else {
+      const void* Mf[kMaxGroup];
+      const void* Mh[kMaxGroup];
+      const void* Ml[kMaxGroup];
+      const double* Y[kMaxGroup];
+      for (int k = 0; k < tg.count; ++k) {
+        Mf[k] = tg.M[k][mu];
+        Mh[k] = tg.Mh[k][mu];
+        Ml[k] = tg.Ml[k][mu];
+        Y[k] = last ? tg.Y[k] : nullptr;
+      }
+      const long long X = g.N / g.n[mu];
+      e = timed(kKindMode, s, [&] {
+        return launch_tgemm_lowp(precision, W, Mf, Mh, Ml, out, Y, tg.count, g.n[mu], X,
+                                 last ? alpha : 1.0, last ? beta : 0.0, last ? 1 : 0, s);
+      });
+    }
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -149,7 +169,9 @@ struct Carve {
   double* V2 = nullptr;
   void* R[4] = {};
   void* T[4] = {};
-  float* phi32[2][3][3] = {};
+  float* phi32[2][3][3] = {};            // FP32 copies (ADR_F32)
+  unsigned short* phih[2][3][3] = {};    // split-BF16 parts, transposed (ADR_BF16X3)
+  unsigned short* phil[2][3][3] = {};
   size_t bytes = 0;
 };
 
@@ -173,9 +195,15 @@ Carve carve(const adr_problem* p, const Geometry& g, char* base) {
   if (lowp) {
     for (int cc = 0; cc < 2; ++cc)
       for (int j = 0; j < 3; ++j)
-        for (int mu = 0; mu < g.d; ++mu)
-          c.phi32[cc][j][mu] =
-              static_cast<float*>(take(align_up((size_t)g.n[mu] * g.n[mu] * sizeof(float))));
+        for (int mu = 0; mu < g.d; ++mu) {
+          const size_t nn = (size_t)g.n[mu] * g.n[mu];
+          if (p->precision == ADR_F32) {
+            c.phi32[cc][j][mu] = static_cast<float*>(take(align_up(nn * sizeof(float))));
+          } else {
+            c.phih[cc][j][mu] = static_cast<unsigned short*>(take(align_up(nn * 2)));
+            c.phil[cc][j][mu] = static_cast<unsigned short*>(take(align_up(nn * 2)));
+          }
+        }
   }
   c.bytes = off;
   return c;
@@ -196,15 +224,27 @@ hipError_t prepare_lowp(const adr_problem* p, const Geometry& g, const Carve& c,
       for (int mu = 0; mu < g.d; ++mu) {
         const double* src = p->phi[cc][j][mu];
         if (!src) continue;
-        hipError_t e = launch_convert_f64_f32(src, c.phi32[cc][j][mu], (size_t)g.n[mu] * g.n[mu], s);
+        hipError_t e = (p->precision == ADR_F32)
+                           ? launch_convert_f64_f32(src, c.phi32[cc][j][mu],
+                                                    (size_t)g.n[mu] * g.n[mu], s)
+                           : launch_split_bf16(g.n[mu], src, c.phih[cc][j][mu],
+                                               c.phil[cc][j][mu], s);
         if (e != hipSuccess) return e;
       }
   return hipSuccess;
 }
 
-const double* phi_ptr(const adr_problem* p, const Carve& c, int comp, int j, int mu) {
-  if (p->precision == ADR_F64) return p->phi[comp][j][mu];
-  return reinterpret_cast<const double*>(c.phi32[comp][j][mu]);
+// Small matrices of (component, function j, direction mu) in the form the
+// step's precision consumes.
+void set_phi(TuckerGroup& tg, int k, const adr_problem* p, const Carve& c, int comp, int j, int mu) {
+  if (p->precision == ADR_F64) {
+    tg.M[k][mu] = p->phi[comp][j][mu];
+  } else if (p->precision == ADR_F32) {
+    tg.M[k][mu] = reinterpret_cast<const double*>(c.phi32[comp][j][mu]);
+  } else {
+    tg.Mh[k][mu] = c.phih[comp][j][mu];
+    tg.Ml[k][mu] = c.phil[comp][j][mu];
+  }
 }
 
 hipError_t step_etd2rkds(const adr_problem* p, const Geometry& g, const Carve& c, double* U,
@@ -258,7 +298,7 @@ hipError_t step_etd2rkds(const adr_problem* p, const Geometry& g, const Carve& c
     tg.in[cc] = c.R[cc];
     tg.t1[cc] = c.T[cc];
     tg.t2[cc] = c.R[cc];
-    for (int mu = 0; mu < g.d; ++mu) tg.M[cc][mu] = phi_ptr(p, c, cc, 1, mu);
+    for (int mu = 0; mu < g.d; ++mu) set_phi(tg, cc, p, c, cc, 1, mu);
   }
   tg.out[0] = c.U2;
   tg.out[1] = c.V2;
@@ -273,7 +313,7 @@ hipError_t step_etd2rkds(const adr_problem* p, const Geometry& g, const Carve& c
   if (e != hipSuccess) return e;
   // C_{n+1} = C_{n2} + 2^(d-1) tau * Tucker(R^c; phi_2)
   for (int cc = 0; cc < 2; ++cc)
-    for (int mu = 0; mu < g.d; ++mu) tg.M[cc][mu] = phi_ptr(p, c, cc, 2, mu);
+    for (int mu = 0; mu < g.d; ++mu) set_phi(tg, cc, p, c, cc, 2, mu);
   tg.out[0] = U;
   tg.out[1] = V;
   tg.Y[0] = c.U2;
@@ -300,7 +340,7 @@ hipError_t step_lawson2b(const adr_problem* p, const Geometry& g, const Carve& c
     tg.in[k] = c.R[k];
     tg.t1[k] = c.T[k];
     tg.t2[k] = c.R[k];
-    for (int mu = 0; mu < g.d; ++mu) tg.M[k][mu] = phi_ptr(p, c, cc, 0, mu);
+    for (int mu = 0; mu < g.d; ++mu) set_phi(tg, k, p, c, cc, 0, mu);
   }
   tg.out[0] = c.U2;
   tg.out[1] = c.V2;

@@ -33,8 +33,18 @@ struct ModeArgs {
 
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_mode_product_f64(const ModeArgs& a, hipStream_t s);
-hipError_t launch_mode_product_f32(const ModeArgs& a, int in_f32, int out_f32, hipStream_t s);
-hipError_t launch_mode_product_bf16x3(const ModeArgs& a, int in_f32, int out_f32, hipStream_t s);
+
+// Reduced-precision "transposing" product (precision 1 = FP32, 2 = split BF16):
+//   out[x + X*i] = alpha * sum_k M[i,k] W[k + n*x] (+ beta * Y[x + X*i])
+// W: FP32 n x X column-major; M: FP32 n x n column-major (FP32) or transposed
+// bf16 hi/lo parts (BF16X3); out: FP32, or FP64 with the FP64 addend Y.
+hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* const* Mf32,
+                             const void* const* Mh, const void* const* Ml, void* const* out,
+                             const double* const* Y, int group, int n, long long X, double alpha,
+                             double beta, int out_f64, hipStream_t s);
+// Split an FP64 n x n column-major matrix into transposed bf16 hi/lo parts.
+hipError_t launch_split_bf16(int n, const double* M, unsigned short* Mh, unsigned short* Ml,
+                             hipStream_t s);
 
 // Reaction model constants as passed to the stage kernels.
 struct Reaction {

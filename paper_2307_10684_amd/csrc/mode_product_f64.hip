@@ -314,6 +314,23 @@ __global__ __launch_bounds__(64 * WI * WX, 2) void k_mode_f64_persist(ModeArgs a
     return (k < per && t < ntiles) ? t : -1;
   };
 
+  // output element of accumulator (fi, fx, v) of this lane: a tile base (uniform)
+  // + a lane offset + a constant, since a tile's fibres never straddle a batch
+  // (L % BX == 0 is a launch condition of this kernel)
+  const unsigned lane_off = !KFAST ? (unsigned)(wx * TX + col) + L * (unsigned)(wi * TI + krow)
+                                   : (unsigned)(wx * TX + krow) * (unsigned)n + (unsigned)(wi * TI + col);
+  auto out_index = [&](const TileDesc& d, int fi, int fx, int v) -> unsigned {
+    if (!KFAST) {
+      const unsigned base = (d.x0 % L) + Ln * (d.x0 / L) + L * (unsigned)d.i0;
+      return base + lane_off + (unsigned)(fx * 16) + L * (unsigned)(fi * 16 + 4 * v);
+    }
+    const unsigned base = d.x0 * (unsigned)n + (unsigned)d.i0;
+    return base + lane_off + (unsigned)((fx * 16 + 4 * v) * n) + (unsigned)(fi * 16);
+  };
+  // (only for x-contiguous products: in the FP64 Tucker chain the last product,
+  // which carries the addend, is x-contiguous whenever d > 1)
+  const bool y_in_acc = !KFAST && a.alpha != 0.0;
+
   const int m_j = tid % MPR, m_k0 = tid / MPR;
   const int w_j = KFAST ? tid % KPR : tid % WPR;
   const int w_b = KFAST ? tid / KPR : tid / WPR;
@@ -366,11 +383,28 @@ __global__ __launch_bounds__(64 * WI * WX, 2) void k_mode_f64_persist(ModeArgs a
   while (true) {
     const int tn = tile_index(k + 1);
     const TileDesc nxt = tile_of(tn < 0 ? 0 : tn);
+    // With an addend, the accumulators start from (beta/alpha) * Y: the loads
+    // are issued together at the start of the tile (one memory latency, hidden
+    // behind the first chunk) instead of in the epilogue, and the epilogue is a
+    // pure store of alpha * acc.
+    double* out = static_cast<double*>(const_cast<void*>(pick(a.out, cur.g)));
+    const double* Y = y_in_acc ? static_cast<const double*>(pick(reinterpret_cast<const void* const*>(a.Y), cur.g)) : nullptr;
+    const double* Z = static_cast<const double*>(pick(reinterpret_cast<const void* const*>(a.Z), cur.g));
     d4 acc[FI][FX];
+    if (!KFAST && Y) {
+      const double ys = beta / alpha;
 #pragma unroll
-    for (int fi = 0; fi < FI; ++fi)
+      for (int fi = 0; fi < FI; ++fi)
 #pragma unroll
-      for (int fx = 0; fx < FX; ++fx) acc[fi][fx] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int fx = 0; fx < FX; ++fx)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[fi][fx][v] = ys * Y[out_index(cur, fi, fx, v)];
+    } else {
+#pragma unroll
+      for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+        for (int fx = 0; fx < FX; ++fx) acc[fi][fx] = d4{0.0, 0.0, 0.0, 0.0};
+    }
 
     for (int c = 0; c < nchunks; ++c) {
       // next chunk: the following one of this tile, or the first of the next tile
@@ -409,42 +443,19 @@ __global__ __launch_bounds__(64 * WI * WX, 2) void k_mode_f64_persist(ModeArgs a
     }
 
     // epilogue of the current tile (the next tile's first chunk is already in LDS)
-    double* out = static_cast<double*>(const_cast<void*>(pick(a.out, cur.g)));
-    const double* Y = static_cast<const double*>(pick(reinterpret_cast<const void* const*>(a.Y), cur.g));
-    const double* Z = static_cast<const double*>(pick(reinterpret_cast<const void* const*>(a.Z), cur.g));
-    if (!KFAST) {
+    const double* Ye = y_in_acc ? nullptr : static_cast<const double*>(pick(reinterpret_cast<const void* const*>(a.Y), cur.g));
 #pragma unroll
-      for (int fx = 0; fx < FX; ++fx) {
-        const unsigned x = cur.x0 + wx * TX + fx * 16 + col;
-        const unsigned xo = (x % L) + Ln * (x / L);
+    for (int fi = 0; fi < FI; ++fi)
 #pragma unroll
-        for (int fi = 0; fi < FI; ++fi)
+      for (int fx = 0; fx < FX; ++fx)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const unsigned o = xo + L * (unsigned)(cur.i0 + wi * TI + fi * 16 + krow + 4 * v);
-            double val = alpha * acc[fi][fx][v];
-            if (Y) val += beta * Y[o];
-            if (Z) val += gamma * Z[o];
-            out[o] = val;
-          }
-      }
-    } else {
-#pragma unroll
-      for (int fi = 0; fi < FI; ++fi) {
-        const unsigned i = (unsigned)(cur.i0 + wi * TI + fi * 16 + col);
-#pragma unroll
-        for (int fx = 0; fx < FX; ++fx)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const unsigned x = cur.x0 + wx * TX + fx * 16 + krow + 4 * v;
-            const unsigned o = x * (unsigned)n + i;
-            double val = alpha * acc[fi][fx][v];
-            if (Y) val += beta * Y[o];
-            if (Z) val += gamma * Z[o];
-            out[o] = val;
-          }
-      }
-    }
+        for (int v = 0; v < 4; ++v) {
+          const unsigned o = out_index(cur, fi, fx, v);
+          double val = alpha * acc[fi][fx][v];
+          if (Ye) val += beta * Ye[o];
+          if (Z) val += gamma * Z[o];
+          out[o] = val;
+        }
     if (tn < 0) break;
     cur = nxt;
     ++k;
@@ -465,9 +476,9 @@ int device_cu_count() {
 
 template <int BI, int BX, int WI, int WX, int BK>
 bool launch_persist(const ModeArgs& a, hipStream_t s, hipError_t& err) {
-  // evenly tiled, pair-aligned shapes only
+  // evenly tiled, pair-aligned shapes only; a tile's fibres stay within one batch
   if (a.n % BI != 0 || a.n % BK != 0 || a.X % BX != 0) return false;
-  if (a.L != 1 && a.L % 2 != 0) return false;
+  if (a.L != 1 && a.L % BX != 0) return false;
   if (a.n % 2 != 0) return false;
   for (int g = 0; g < a.group; ++g)
     if ((reinterpret_cast<uintptr_t>(a.W[g]) | reinterpret_cast<uintptr_t>(a.M[g])) % 16 != 0)

@@ -1,13 +1,424 @@
-// Reduced-precision mu-mode products (FP32 and split-BF16); filled in below.
+// Reduced-precision mu-mode products for the Tucker operators of the step
+// (the state, the stage combinations and the small matrix functions stay
+// FP64; only the bulk products run in lower precision):
+//
+//   FP32      v_mfma_f32_16x16x4_f32 on FP32 data;
+//   BF16X3    each FP32 operand x is split as x = hi + lo with hi = bf16(x),
+//             lo = bf16(x - hi), and a*b is taken as hi_a hi_b + hi_a lo_b +
+//             lo_a hi_b on v_mfma_f32_16x16x32_bf16 with FP32 accumulation (the
+//             lo_a lo_b term, ~2^-16 relative, is dropped).
+//
+// Both use one "transposing" product form,
+//
+//   out[x + X*i] = alpha * sum_k M[i,k] W[k + n*x]  (+ beta * Y[x + X*i]),
+//
+// i.e. the input fibres are contiguous and the output is written with the
+// fibre index fastest.  Chaining d of these rotates the tensor layout
+// (n1,n2,n3) -> (n2,n3,n1) -> (n3,n1,n2) -> (n1,n2,n3): every product of the
+// Tucker operator reads contiguous fibres and the last one writes the
+// natural layout again.  The host drives the chain (run_tucker in adr_api).
+//
+// Fragment layouts (wave64, probed on gfx950): f32 16x16x4 takes A[l%16][l/16],
+// B[l/16][l%16]; bf16 16x16x32 takes A[l%16][8(l/16)+j], B[8(l/16)+j][l%16],
+// j = 0..7; both return D[4(l/16)+v][l%16], v = 0..3.
 #include "common.h"
 
 namespace adr {
+namespace {
 
-hipError_t launch_mode_product_f32(const ModeArgs&, int, int, hipStream_t) {
-  return hipErrorNotSupported;
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+
+// float -> bf16 bits, round to nearest even (inputs are finite)
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+  const unsigned u = __float_as_uint(x);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
-hipError_t launch_mode_product_bf16x3(const ModeArgs&, int, int, hipStream_t) {
-  return hipErrorNotSupported;
+__device__ __forceinline__ float bf16_float(unsigned short b) {
+  return __uint_as_float((unsigned)b << 16);
+}
+
+struct LowpArgs {
+  const float* W[kMaxGroup];     // inputs, n x X column-major (fibres contiguous)
+  const float* M[kMaxGroup];     // FP32: n x n column-major
+  const unsigned short* Mh[kMaxGroup];  // BF16X3: transposed hi/lo parts, k fastest
+  const unsigned short* Ml[kMaxGroup];
+  void* out[kMaxGroup];          // FP32 (rotated) or FP64 (last product)
+  const double* Y[kMaxGroup];    // FP64 addend for the last product, may alias out
+  double alpha, beta;
+  int n;
+  unsigned X;
+  int group;
+};
+
+constexpr int kThreads = 256;
+
+// Epilogue of a wave's TI x TX block of D[i][x] (lane: rows 4*krow + v of each
+// 16x16 block, column col).  For the FP64 output all addends of one 16-column
+// strip are loaded before any result is formed, so their latencies overlap.
+template <int FI, int FX, int TI, int TX, bool OUT64>
+__device__ __forceinline__ void tgemm_epilogue(const LowpArgs& a, int g, const f4 (&acc)[FI][FX],
+                                               int ib, unsigned xb, int col, int krow) {
+  const int n = a.n;
+  const unsigned X = a.X;
+  const double alpha = a.alpha, beta = a.beta;
+  const double* Y = a.Y[g];
+#pragma unroll
+  for (int fx = 0; fx < FX; ++fx) {
+    const unsigned x = xb + fx * 16 + col;
+    const bool xok = x < X;
+    if (OUT64) {
+      double y[FI][4];
+#pragma unroll
+      for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = ib + fi * 16 + 4 * krow + v;
+          const bool ok = xok && i < n && Y != nullptr;
+          y[fi][v] = ok ? Y[x + X * (unsigned)i] : 0.0;
+        }
+      double* out = static_cast<double*>(a.out[g]);
+#pragma unroll
+      for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = ib + fi * 16 + 4 * krow + v;
+          if (xok && i < n) out[x + X * (unsigned)i] = alpha * (double)acc[fi][fx][v] + beta * y[fi][v];
+        }
+    } else {
+      float* out = static_cast<float*>(a.out[g]);
+#pragma unroll
+      for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = ib + fi * 16 + 4 * krow + v;
+          if (xok && i < n) out[x + X * (unsigned)i] = (float)(alpha * (double)acc[fi][fx][v]);
+        }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ FP32
+// Tile: BI rows i x BX fibres x, BK = 16 per chunk, four waves in a 2x2 grid.
+template <int BI, int BX, bool OUT64>
+__global__ __launch_bounds__(kThreads, 2) void k_tgemm_f32(LowpArgs a, int n_itiles,
+                                                          int n_xtiles) {
+  constexpr int BK = 16;
+  constexpr int WI = 2, WX = 2;
+  constexpr int TI = BI / WI, TX = BX / WX, FI = TI / 16, FX = TX / 16;
+  constexpr int LDI = BI + 32;   // [k][i] rows: next k-row 32 banks away
+  constexpr int LDK = BK + 1;    // [x][k] rows: odd pitch, conflict-free fragments
+  constexpr int MROWS = kThreads / BI, MLOADS = BK / MROWS;
+  constexpr int XSTEP = kThreads / BK, WLOADS = BX / XSTEP;
+  static_assert(MROWS * BI == kThreads && XSTEP * BK == kThreads, "mapping");
+  __shared__ float sM[2][BK * LDI];
+  __shared__ float sW[2][BX * LDK];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave / WX, wx = wave % WX;
+  const int G = gridDim.x, b = blockIdx.x;
+  int t = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  const int itile = t % n_itiles;
+  t /= n_itiles;
+  const int xtile = t % n_xtiles;
+  const int g = t / n_xtiles;
+  const int n = a.n;
+  const unsigned X = a.X;
+  const int i0 = itile * BI;
+  const unsigned x0 = (unsigned)xtile * BX;
+  const float* __restrict__ W = a.W[g];
+  const float* __restrict__ M = a.M[g];
+
+  const int m_i = tid % BI, m_k0 = tid / BI;
+  const int w_k = tid % BK, w_x0 = tid / BK;
+  float rm[MLOADS], rw[WLOADS];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < MLOADS; ++p) {
+      const int i = i0 + m_i, k = k0 + m_k0 + p * MROWS;
+      const bool ok = i < n && k < n;
+      rm[p] = M[ok ? (unsigned)i + (unsigned)n * (unsigned)k : 0u];
+    }
+#pragma unroll
+    for (int p = 0; p < WLOADS; ++p) {
+      const unsigned x = x0 + w_x0 + p * XSTEP;
+      const int k = k0 + w_k;
+      const bool ok = x < X && k < n;
+      rw[p] = W[ok ? x * (unsigned)n + (unsigned)k : 0u];
+    }
+  };
+  auto store = [&](int buf, int k0) {
+#pragma unroll
+    for (int p = 0; p < MLOADS; ++p) {
+      const bool ok = (i0 + m_i) < n && (k0 + m_k0 + p * MROWS) < n;
+      sM[buf][(m_k0 + p * MROWS) * LDI + m_i] = ok ? rm[p] : 0.0f;
+    }
+#pragma unroll
+    for (int p = 0; p < WLOADS; ++p) {
+      const bool ok = (x0 + w_x0 + p * XSTEP) < X && (k0 + w_k) < n;
+      sW[buf][(w_x0 + p * XSTEP) * LDK + w_k] = ok ? rw[p] : 0.0f;
+    }
+  };
+
+  f4 acc[FI][FX];
+#pragma unroll
+  for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+    for (int fx = 0; fx < FX; ++fx) acc[fi][fx] = f4{0.f, 0.f, 0.f, 0.f};
+  const int nchunks = (n + BK - 1) / BK;
+  load(0);
+  store(0, 0);
+  __syncthreads();
+  const int col = lane & 15, krow = lane >> 4;
+  for (int c = 0; c < nchunks; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nchunks) load((c + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + krow;
+      float af[FI], bfr[FX];
+#pragma unroll
+      for (int fi = 0; fi < FI; ++fi) af[fi] = sM[buf][kr * LDI + wi * TI + fi * 16 + col];
+#pragma unroll
+      for (int fx = 0; fx < FX; ++fx) bfr[fx] = sW[buf][(wx * TX + fx * 16 + col) * LDK + kr];
+#pragma unroll
+      for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+        for (int fx = 0; fx < FX; ++fx)
+          acc[fi][fx] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[fi], bfr[fx], acc[fi][fx], 0, 0, 0);
+    }
+    if (c + 1 < nchunks) store(buf ^ 1, (c + 1) * BK);
+    __syncthreads();
+  }
+  // D[i][x]: lane holds rows i = 4*krow + v, column x = col
+  tgemm_epilogue<FI, FX, TI, TX, OUT64>(a, g, acc, i0 + wi * TI, x0 + wx * TX, col, krow);
+}
+
+// ------------------------------------------------------------------ split BF16
+// Tile: BI rows i x BX fibres, BK = 32 (one bf16 MFMA depth) per chunk.  The W
+// chunk is loaded as FP32 (eight consecutive k per lane), split into hi/lo and
+// stored k-fastest; M arrives pre-split and transposed (k fastest).
+template <int BI, int BX, bool OUT64, bool FULL>
+__global__ __launch_bounds__(kThreads, 2) void k_tgemm_bf16x3(LowpArgs a, int n_itiles,
+                                                             int n_xtiles) {
+  constexpr int BK = 32;
+  constexpr int WI = 2, WX = 2;
+  constexpr int TI = BI / WI, TX = BX / WX, FI = TI / 16, FX = TX / 16;
+  constexpr int LDK = BK + 8;               // bf16 elements per row: 80 B pitch, conflict-free b128 reads
+  constexpr int MSEG = BI * (BK / 8);        // 8-element segments of the M chunk
+  constexpr int WSEG = BX * (BK / 8);
+  constexpr int MLOADS = MSEG / kThreads, WLOADS = WSEG / kThreads;
+  static_assert(MLOADS * kThreads == MSEG && WLOADS * kThreads == WSEG, "mapping");
+  __shared__ unsigned short sMh[2][BI * LDK], sMl[2][BI * LDK];
+  __shared__ unsigned short sWh[2][BX * LDK], sWl[2][BX * LDK];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave / WX, wx = wave % WX;
+  const int G = gridDim.x, b = blockIdx.x;
+  int t = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  const int itile = t % n_itiles;
+  t /= n_itiles;
+  const int xtile = t % n_xtiles;
+  const int g = t / n_xtiles;
+  const int n = a.n;
+  const unsigned X = a.X;
+  const int i0 = itile * BI;
+  const unsigned x0 = (unsigned)xtile * BX;
+  const float* __restrict__ W = a.W[g];
+  const unsigned short* __restrict__ Mh = a.Mh[g];
+  const unsigned short* __restrict__ Ml = a.Ml[g];
+
+  // segment s of a chunk: row r = s / 4 (i or x), k-group q = s % 4 (8 k-values)
+  s8 rmh[MLOADS], rml[MLOADS];
+  float rw[WLOADS][8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < MLOADS; ++p) {
+      const int s = tid + p * kThreads, r = s >> 2, q = s & 3;
+      const int i = i0 + r, k = k0 + 8 * q;
+      if (FULL) {  // whole tile in range, 16-byte aligned rows
+        const unsigned idx = (unsigned)i * (unsigned)n + (unsigned)k;
+        rmh[p] = *reinterpret_cast<const s8*>(Mh + idx);
+        rml[p] = *reinterpret_cast<const s8*>(Ml + idx);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const bool ok = i < n && (k + j) < n;
+          const unsigned idx = ok ? (unsigned)i * (unsigned)n + (unsigned)(k + j) : 0u;
+          rmh[p][j] = ok ? (short)Mh[idx] : (short)0;
+          rml[p][j] = ok ? (short)Ml[idx] : (short)0;
+        }
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < WLOADS; ++p) {
+      const int s = tid + p * kThreads, r = s >> 2, q = s & 3;
+      const unsigned x = x0 + r;
+      const int k = k0 + 8 * q;
+      if (FULL) {
+        const f4* src = reinterpret_cast<const f4*>(W + x * (unsigned)n + (unsigned)k);
+        const f4 lo4 = src[0], hi4 = src[1];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          rw[p][j] = lo4[j];
+          rw[p][4 + j] = hi4[j];
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const bool ok = x < X && (k + j) < n;
+          rw[p][j] = ok ? W[x * (unsigned)n + (unsigned)(k + j)] : 0.0f;
+        }
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < MLOADS; ++p) {
+      const int s = tid + p * kThreads, r = s >> 2, q = s & 3;
+      *reinterpret_cast<s8*>(&sMh[buf][r * LDK + 8 * q]) = rmh[p];
+      *reinterpret_cast<s8*>(&sMl[buf][r * LDK + 8 * q]) = rml[p];
+    }
+#pragma unroll
+    for (int p = 0; p < WLOADS; ++p) {
+      const int s = tid + p * kThreads, r = s >> 2, q = s & 3;
+      s8 h, l;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const unsigned short hb = bf16_bits(rw[p][j]);
+        h[j] = (short)hb;
+        l[j] = (short)bf16_bits(rw[p][j] - bf16_float(hb));
+      }
+      *reinterpret_cast<s8*>(&sWh[buf][r * LDK + 8 * q]) = h;
+      *reinterpret_cast<s8*>(&sWl[buf][r * LDK + 8 * q]) = l;
+    }
+  };
+
+  f4 acc[FI][FX];
+#pragma unroll
+  for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+    for (int fx = 0; fx < FX; ++fx) acc[fi][fx] = f4{0.f, 0.f, 0.f, 0.f};
+  const int nchunks = (n + BK - 1) / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  const int col = lane & 15, kq = lane >> 4;
+  for (int c = 0; c < nchunks; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nchunks) load((c + 1) * BK);
+    s8 ah[FI], al[FI], bh[FX], bl[FX];
+#pragma unroll
+    for (int fi = 0; fi < FI; ++fi) {
+      const int r = wi * TI + fi * 16 + col;
+      ah[fi] = *reinterpret_cast<const s8*>(&sMh[buf][r * LDK + 8 * kq]);
+      al[fi] = *reinterpret_cast<const s8*>(&sMl[buf][r * LDK + 8 * kq]);
+    }
+#pragma unroll
+    for (int fx = 0; fx < FX; ++fx) {
+      const int r = wx * TX + fx * 16 + col;
+      bh[fx] = *reinterpret_cast<const s8*>(&sWh[buf][r * LDK + 8 * kq]);
+      bl[fx] = *reinterpret_cast<const s8*>(&sWl[buf][r * LDK + 8 * kq]);
+    }
+#pragma unroll
+    for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+      for (int fx = 0; fx < FX; ++fx) {
+        // small terms first, the dominant product last
+        acc[fi][fx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[fi], bh[fx], acc[fi][fx], 0, 0, 0);
+        acc[fi][fx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[fi], bl[fx], acc[fi][fx], 0, 0, 0);
+        acc[fi][fx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[fi], bh[fx], acc[fi][fx], 0, 0, 0);
+      }
+    if (c + 1 < nchunks) store(buf ^ 1);
+    __syncthreads();
+  }
+  tgemm_epilogue<FI, FX, TI, TX, OUT64>(a, g, acc, i0 + wi * TI, x0 + wx * TX, col, kq);
+}
+
+// Split an FP64 n x n column-major matrix into transposed bf16 hi/lo parts:
+// Mh[i*n + k] + Ml[i*n + k] ~ M[i + n*k] (via FP32).
+__global__ __launch_bounds__(256) void k_split_bf16(int n, const double* __restrict__ M,
+                                                    unsigned short* __restrict__ Mh,
+                                                    unsigned short* __restrict__ Ml) {
+  const long long nn = (long long)n * n;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < nn;
+       q += (long long)gridDim.x * blockDim.x) {
+    const long long i = q / n, k = q % n;   // q = i*n + k
+    const float x = (float)M[i + (long long)n * k];
+    const unsigned short h = bf16_bits(x);
+    Mh[q] = h;
+    Ml[q] = bf16_bits(x - bf16_float(h));
+  }
+}
+
+template <class K>
+hipError_t launch_tiles(K kern, const LowpArgs& a, int BI, int BX, hipStream_t s) {
+  const int n_itiles = (a.n + BI - 1) / BI;
+  const long long n_xtiles = ((long long)a.X + BX - 1) / BX;
+  const long long grid = (long long)a.group * n_itiles * n_xtiles;
+  if (grid <= 0 || grid > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kThreads), 0, s, a, n_itiles, (int)n_xtiles);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* const* Mf32,
+                             const void* const* Mh, const void* const* Ml, void* const* out,
+                             const double* const* Y, int group, int n, long long X, double alpha,
+                             double beta, int out_f64, hipStream_t s) {
+  if (group < 1 || group > kMaxGroup || X <= 0 || X >= (1LL << 31) ||
+      (long long)n * X >= (1LL << 31))
+    return hipErrorInvalidValue;
+  LowpArgs a{};
+  for (int g = 0; g < group; ++g) {
+    a.W[g] = static_cast<const float*>(W[g]);
+    a.M[g] = Mf32 ? static_cast<const float*>(Mf32[g]) : nullptr;
+    a.Mh[g] = Mh ? static_cast<const unsigned short*>(Mh[g]) : nullptr;
+    a.Ml[g] = Ml ? static_cast<const unsigned short*>(Ml[g]) : nullptr;
+    a.out[g] = out[g];
+    a.Y[g] = Y ? Y[g] : nullptr;
+  }
+  a.alpha = alpha;
+  a.beta = beta;
+  a.n = n;
+  a.X = (unsigned)X;
+  a.group = group;
+  if (precision == 1) {
+    if (n <= 64)
+      return out_f64 ? launch_tiles(k_tgemm_f32<64, 128, true>, a, 64, 128, s)
+                     : launch_tiles(k_tgemm_f32<64, 128, false>, a, 64, 128, s);
+    return out_f64 ? launch_tiles(k_tgemm_f32<128, 128, true>, a, 128, 128, s)
+                   : launch_tiles(k_tgemm_f32<128, 128, false>, a, 128, 128, s);
+  }
+  // evenly tiled shapes with 16-byte aligned fibres take the vectorised loads
+  bool aligned = true;
+  for (int g = 0; g < group; ++g)
+    aligned = aligned && (reinterpret_cast<uintptr_t>(W[g]) % 16 == 0) &&
+              (reinterpret_cast<uintptr_t>(Mh[g]) % 16 == 0) &&
+              (reinterpret_cast<uintptr_t>(Ml[g]) % 16 == 0);
+  if (n <= 64) {
+    const bool full = aligned && n % 64 == 0 && X % 128 == 0;
+    if (full)
+      return out_f64 ? launch_tiles(k_tgemm_bf16x3<64, 128, true, true>, a, 64, 128, s)
+                     : launch_tiles(k_tgemm_bf16x3<64, 128, false, true>, a, 64, 128, s);
+    return out_f64 ? launch_tiles(k_tgemm_bf16x3<64, 128, true, false>, a, 64, 128, s)
+                   : launch_tiles(k_tgemm_bf16x3<64, 128, false, false>, a, 64, 128, s);
+  }
+  const bool full = aligned && n % 128 == 0 && X % 128 == 0;
+  if (full)
+    return out_f64 ? launch_tiles(k_tgemm_bf16x3<128, 128, true, true>, a, 128, 128, s)
+                   : launch_tiles(k_tgemm_bf16x3<128, 128, false, true>, a, 128, 128, s);
+  return out_f64 ? launch_tiles(k_tgemm_bf16x3<128, 128, true, false>, a, 128, 128, s)
+                 : launch_tiles(k_tgemm_bf16x3<128, 128, false, false>, a, 128, 128, s);
+}
+
+hipError_t launch_split_bf16(int n, const double* M, unsigned short* Mh, unsigned short* Ml,
+                             hipStream_t s) {
+  long long blocks = ((long long)n * n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)blocks), dim3(256), 0, s, n, M, Mh, Ml);
+  return hipGetLastError();
 }
 
 }  // namespace adr

@@ -41,17 +41,15 @@ __device__ __forceinline__ void put(void* p, long long q, double x) {
 
 // Stage 1: R^c = sum_mu (C x_mu A_mu^c) + G^c(U, V) for the directions with a
 // band; directions without one are added afterwards by dense mode products.
-// Block = (64, 4) threads over (i_1, i_2); each block marches through ZB planes
-// of i_3.  The loop is software-pipelined: while plane z is computed, the
-// values of plane z+1 that a thread needs (its own point, its i_2 +- 1
-// neighbours and, on the wave edges, its i_1 +- 1 neighbours) are already in
-// flight, and the i_3 neighbours are the previous / next planes held in
-// registers.  Inside a wave the i_1 +- 1 neighbours come from lane shuffles.
+// Block = (64, 4) threads over (i_1, i_2); each block marches through kZB planes
+// of i_3.  A plane's centre value is loaded once: it serves as the i_3 + 1
+// neighbour of the plane before, then as the centre, then as the i_3 - 1
+// neighbour.  Inside a wave the i_1 +- 1 neighbours come from lane shuffles
+// (the wave-edge lanes load theirs); the i_2 +- 1 neighbours are loads that
+// the neighbouring rows of the block have just brought into the L1 cache.
+// Loads are branch-free (clamped index, then masked).  Latency is hidden by
+// occupancy: the kernel keeps few registers so that many waves share a SIMD.
 constexpr int kZB = 16;  // planes per block
-
-struct Plane {
-  double c, ym, yp, xm, xp;  // centre, i_2 -+ 1, i_1 -+ 1 (wave-edge lanes only)
-};
 
 template <typename TR>
 __global__ __launch_bounds__(256) void k_etd_stage1(StageGeom g, Reaction r,
@@ -60,78 +58,91 @@ __global__ __launch_bounds__(256) void k_etd_stage1(StageGeom g, Reaction r,
                                                     void* Rv) {
   const int n1 = g.n[0], n2 = g.d >= 2 ? g.n[1] : 1, n3 = g.d >= 3 ? g.n[2] : 1;
   const int i1 = blockIdx.x * 64 + threadIdx.x;
-  const int i2 = blockIdx.y * 4 + threadIdx.y;
+  // i_2 is the same on the whole wave (blockDim.x = 64): keep it in a scalar
+  // register so its band coefficients are scalar loads
+  const int i2 = __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + threadIdx.y);
   const int z0 = blockIdx.z * kZB;
   const int z1 = min(z0 + kZB, n3);
   const bool live = i1 < n1 && i2 < n2;
   const unsigned P = (unsigned)n1 * (unsigned)n2;  // plane stride
   const int lane = threadIdx.x;
-  // per-thread band coefficients of directions 1 and 2 (zero where there is no
-  // neighbour and where the direction has no band)
+  const int tid = threadIdx.y * 64 + threadIdx.x;
+
+  // i_3 band coefficients of this block's planes (zero without a band)
+  __shared__ double sb3[2][3][kZB];
+  if (tid < 2 * 3 * kZB) {
+    const int c = tid / (3 * kZB), j = (tid / kZB) % 3, zz = tid % kZB, z = z0 + zz;
+    const double* b = g.d >= 3 ? g.band[c][2] : nullptr;
+    sb3[c][j][zz] = (b && z < n3) ? b[j * n3 + z] : 0.0;
+  }
+  // per-thread band coefficients of directions 1 and 2
   double a1u[3] = {0, 0, 0}, a1v[3] = {0, 0, 0}, a2u[3] = {0, 0, 0}, a2v[3] = {0, 0, 0};
   if (live) {
     if (g.band[0][0]) for (int j = 0; j < 3; ++j) a1u[j] = g.band[0][0][j * n1 + i1];
     if (g.band[1][0]) for (int j = 0; j < 3; ++j) a1v[j] = g.band[1][0][j * n1 + i1];
-    if (g.d >= 2) {
-      if (g.band[0][1]) for (int j = 0; j < 3; ++j) a2u[j] = g.band[0][1][j * n2 + i2];
-      if (g.band[1][1]) for (int j = 0; j < 3; ++j) a2v[j] = g.band[1][1][j * n2 + i2];
-    }
   }
-  const double* b3u = g.d >= 3 ? g.band[0][2] : nullptr;
-  const double* b3v = g.d >= 3 ? g.band[1][2] : nullptr;
+  if (g.d >= 2 && i2 < n2) {
+    if (g.band[0][1]) for (int j = 0; j < 3; ++j) a2u[j] = g.band[0][1][j * n2 + i2];
+    if (g.band[1][1]) for (int j = 0; j < 3; ++j) a2v[j] = g.band[1][1][j * n2 + i2];
+  }
+  __syncthreads();
   const bool has_m2 = live && i2 > 0, has_p2 = live && i2 + 1 < n2;
   const bool edge_m = live && lane == 0 && i1 > 0;
   const bool edge_p = live && lane == 63 && i1 + 1 < n1;
   const unsigned q0 = (unsigned)i2 * (unsigned)n1 + (unsigned)i1;
 
-  auto fetch = [&](const double* __restrict__ C, int z, Plane& o) {
-    const unsigned q = q0 + (unsigned)z * P;
-    o.c = live ? C[q] : 0.0;
-    o.ym = has_m2 ? C[q - n1] : 0.0;
-    o.yp = has_p2 ? C[q + n1] : 0.0;
-    o.xm = edge_m ? C[q - 1] : 0.0;
-    o.xp = edge_p ? C[q + 1] : 0.0;
-  };
-
-  Plane cu, cv, nu, nv;
-  double pu = 0.0, pv = 0.0;  // plane z-1 centre values
-  if (live && z0 > 0) {
-    pu = U[q0 + (unsigned)(z0 - 1) * P];
-    pv = V[q0 + (unsigned)(z0 - 1) * P];
+  double pu, pv, uc, vc;  // centres of planes z-1 and z
+  {
+    const bool okp = live && z0 > 0;
+    const unsigned qp = okp ? q0 + (unsigned)(z0 - 1) * P : 0u;
+    const unsigned qc = live ? q0 + (unsigned)z0 * P : 0u;
+    const double a = U[qp], b = V[qp], c = U[qc], d = V[qc];
+    pu = okp ? a : 0.0;
+    pv = okp ? b : 0.0;
+    uc = live ? c : 0.0;
+    vc = live ? d : 0.0;
   }
-  fetch(U, z0, cu);
-  fetch(V, z0, cv);
   for (int z = z0; z < z1; ++z) {
+    const unsigned q = q0 + (unsigned)z * P;
     const bool has_n3 = z + 1 < n3;
-    if (has_n3) {
-      fetch(U, z + 1, nu);
-      fetch(V, z + 1, nv);
-    } else {
-      nu = Plane{0, 0, 0, 0, 0};
-      nv = Plane{0, 0, 0, 0, 0};
-    }
+    const bool okn = live && has_n3;
+    const unsigned qn = okn ? q + P : 0u;
+    const unsigned qym = has_m2 ? q - n1 : 0u, qyp = has_p2 ? q + n1 : 0u;
+    const unsigned qxm = edge_m ? q - 1 : 0u, qxp = edge_p ? q + 1 : 0u;
+    const double l_un = U[qn], l_vn = V[qn];
+    const double l_uym = U[qym], l_uyp = U[qyp], l_vym = V[qym], l_vyp = V[qyp];
+    const double l_uxm = U[qxm], l_uxp = U[qxp], l_vxm = V[qxm], l_vxp = V[qxp];
+    const double un = okn ? l_un : 0.0, vn = okn ? l_vn : 0.0;
     // i_1 neighbours from the adjacent lanes (the edge lanes use their loads)
-    double um = __shfl_up(cu.c, 1, 64), uq = __shfl_down(cu.c, 1, 64);
-    double vm = __shfl_up(cv.c, 1, 64), vq = __shfl_down(cv.c, 1, 64);
-    if (lane == 0) { um = cu.xm; vm = cv.xm; }
-    if (lane == 63) { uq = cu.xp; vq = cv.xp; }
+    double um = __shfl_up(uc, 1, 64), uq = __shfl_down(uc, 1, 64);
+    double vm = __shfl_up(vc, 1, 64), vq = __shfl_down(vc, 1, 64);
+    if (lane == 0) {
+      um = edge_m ? l_uxm : 0.0;
+      vm = edge_m ? l_vxm : 0.0;
+    }
+    if (lane == 63) {
+      uq = edge_p ? l_uxp : 0.0;
+      vq = edge_p ? l_vxp : 0.0;
+    }
+    const double uym = has_m2 ? l_uym : 0.0, uyp = has_p2 ? l_uyp : 0.0;
+    const double vym = has_m2 ? l_vym : 0.0, vyp = has_p2 ? l_vyp : 0.0;
     if (live) {
+      const int zz = z - z0;
       double gu, gv;
-      react(r, cu.c, cv.c, gu, gv);
-      double ku = a1u[0] * um + a1u[1] * cu.c + a1u[2] * uq;
-      double kv = a1v[0] * vm + a1v[1] * cv.c + a1v[2] * vq;
-      ku += a2u[0] * cu.ym + a2u[1] * cu.c + a2u[2] * cu.yp;
-      kv += a2v[0] * cv.ym + a2v[1] * cv.c + a2v[2] * cv.yp;
-      if (b3u) ku += b3u[z] * pu + b3u[n3 + z] * cu.c + b3u[2 * n3 + z] * nu.c;
-      if (b3v) kv += b3v[z] * pv + b3v[n3 + z] * cv.c + b3v[2 * n3 + z] * nv.c;
-      const unsigned q = q0 + (unsigned)z * P;
+      react(r, uc, vc, gu, gv);
+      double ku = a1u[0] * um + a1u[1] * uc + a1u[2] * uq;
+      double kv = a1v[0] * vm + a1v[1] * vc + a1v[2] * vq;
+      ku += a2u[0] * uym + a2u[1] * uc + a2u[2] * uyp;
+      kv += a2v[0] * vym + a2v[1] * vc + a2v[2] * vyp;
+      ku += sb3[0][0][zz] * pu + sb3[0][1][zz] * uc + sb3[0][2][zz] * un;
+      kv += sb3[1][0][zz] * pv + sb3[1][1][zz] * vc + sb3[1][2][zz] * vn;
       put<TR>(Ru, q, ku + gu);
       put<TR>(Rv, q, kv + gv);
     }
-    pu = cu.c;
-    pv = cv.c;
-    cu = nu;
-    cv = nv;
+    pu = uc;
+    pv = vc;
+    uc = un;
+    vc = vn;
   }
 }
 
