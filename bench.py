@@ -149,7 +149,7 @@ def main(argv=None):
     finite = bool(torch.isfinite(Ud).all().item() and torch.isfinite(Vd).all().item())
 
     # ---- same steps again with per-launch HIP events (kernel durations)
-    launches_per_step = 2 * d + 2
+    launches_per_step = 2 * d + 4
     Ud.copy_(U_init)
     Vd.copy_(V_init)
     torch.cuda.synchronize()
@@ -174,7 +174,11 @@ def main(argv=None):
     bytes_per_launch = 2 * 2 * elem * N  # read + write one tensor per component
     traffic = _traffic_from_profiles(args.precision, w.name)
     stage_avg_ms = ms_stage / max(n_stage, 1)
-    stage_bytes = (32 + 48) / 2 * N  # average of stage 1 (32 B/pt) and stage 2 (48 B/pt)
+    # algorithmic bytes per point of the stage kernels, averaged over the launches of a step:
+    # FP64: stage 1 (read U,V; write R1u,R1v) 32 B, stage 2 (read U,V,U2,V2; write R2) 48 B;
+    # reduced precision: stage 1 24 B (FP32 R1), stage 2 32 B (FP32 D1 in, R2 out),
+    # final C += D1 + D2 48 B
+    stage_bytes = ((32 + 48) / 2 if args.precision == "f64" else (24 + 32 + 48) / 3) * N
 
     line = {
         "metric": METRIC,

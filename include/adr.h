@@ -178,10 +178,62 @@ int adr_tucker(int d, const int32_t* n, const double* const* M, const double* W,
 int adr_device_copy(const double* in, double* out, size_t count, void* stream);
 
 /*
+ * Grouped multi-problem ETD2RKds ("batch plans").  Sec. 3 eq. (11) is applied
+ * to `count` independent problems at once; each problem keeps its own grid
+ * (sizes and dimension may differ), model, constants, tau and small matrices.
+ * Every phase of the step (stage 1, the d mode products of each Tucker
+ * operator, stage 2, and for ADR_F32 the final update) is one launch over all
+ * problems, driven by job tables the plan keeps in device memory, so one step
+ * costs 2*d_max + 2 launches (+1 for ADR_F32) whatever `count` is.
+ *
+ * adr_batch_create -- build a plan.
+ *   problems    host array of `count` (1..4096) problem descriptors; all must
+ *               use ETD2RKds, the same precision (ADR_F64 or ADR_F32) and
+ *               give band[c][mu] for every direction.  The structs are copied;
+ *               the device buffers they point to must stay valid until
+ *               adr_batch_destroy.
+ *   U, V        host arrays of `count` device state pointers (N_i doubles each)
+ *   work        host array of `count` device workspaces, 256-byte aligned, of
+ *               at least adr_workspace_bytes(&problems[i]) bytes; they must not
+ *               overlap each other or any state
+ *   flags       ADR_BATCH_AUTOTUNE: time the tile shapes of every FP64 mode-
+ *               product phase on the plan's own buffers and keep the fastest
+ *               (cached per phase shape for the process; with the environment
+ *               variable ADR_TUNE_CACHE naming a file, also across processes).
+ *               Tuning launches write only workspace, never U or V.
+ *               ADR_BATCH_GRAPH: capture one step in a HIP graph that
+ *               adr_batch_run replays.
+ *   stream      stream for the set-up work (FP32 matrix copies, tuning)
+ *   plan        receives the plan
+ * Errors: ADR_EINVAL, ADR_ENOMEM (a workspace too small, or no device memory
+ * for the tables), ADR_ENOTSUP (scheme, precision or a missing band),
+ * ADR_EDEVICE.
+ */
+typedef struct adr_batch adr_batch;
+enum adr_batch_flags { ADR_BATCH_AUTOTUNE = 1, ADR_BATCH_GRAPH = 2 };
+int adr_batch_create(int count, const adr_problem* problems, double* const* U,
+                     double* const* V, void* const* work, const size_t* work_bytes, int flags,
+                     void* stream, adr_batch** plan);
+/* adr_batch_run -- enqueue nsteps >= 0 steps of every problem of the plan on `stream`. */
+int adr_batch_run(adr_batch* plan, int nsteps, void* stream);
+/*
+ * adr_batch_info -- the tile configuration chosen for the mode products of
+ * each direction mu < max_phases (0: 64x64, 1: 64x128, 2: 128x64, 3: 128x128
+ * rows x fibres; -1 where the plan has no FP64 phase), and whether a graph was
+ * captured.  Either output may be NULL when not wanted (tile_cfg only with
+ * max_phases == 0).
+ */
+int adr_batch_info(const adr_batch* plan, int* tile_cfg, int max_phases, int* graph_captured);
+/* adr_batch_destroy -- release the plan (the caller's buffers are untouched). */
+int adr_batch_destroy(adr_batch* plan);
+
+/*
  * Kernel timing.  adr_timing_enable(capacity) makes later adr_step/adr_solve/
  * adr_tucker/adr_mode_product calls record a HIP event pair around each of
  * their kernel launches, on the stream the kernel runs on, for up to
  * `capacity` launches (capacity 0 disables timing and frees the events).
+ * Batch plans run without a graph are timed the same way, one record per
+ * grouped launch.
  * adr_timing_read synchronises on the recorded events and returns, for the
  * kernel class `kind` (0 = mode product, 1 = stage kernels, 2 = all), the
  * number of launches and their summed duration in milliseconds, then clears

@@ -27,6 +27,7 @@ ADR_BC_NEUMANN = 0
 ADR_ETD2RKDS, ADR_LAWSON2B = 0, 1
 ADR_F64, ADR_F32, ADR_BF16X3 = 0, 1, 2
 ADR_SCHNAKENBERG, ADR_FHN, ADR_BRUSSELATOR, ADR_ZERO = 0, 1, 2, 3
+ADR_BATCH_AUTOTUNE, ADR_BATCH_GRAPH = 1, 2
 
 MODEL_IDS = {"schnakenberg": ADR_SCHNAKENBERG, "fhn": ADR_FHN,
              "brusselator": ADR_BRUSSELATOR, "zero": ADR_ZERO}
@@ -83,6 +84,12 @@ def _load():
         "adr_device_copy": (c_int, [c_void, c_void, c_size, c_void]),
         "adr_timing_enable": (c_int, [c_int]),
         "adr_timing_read": (c_int, [c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_double)]),
+        "adr_batch_create": (c_int, [c_int, ctypes.POINTER(AdrProblem), ctypes.POINTER(c_void),
+                                     ctypes.POINTER(c_void), ctypes.POINTER(c_void),
+                                     ctypes.POINTER(c_size), c_int, c_void, ctypes.POINTER(c_void)]),
+        "adr_batch_run": (c_int, [c_void, c_int, c_void]),
+        "adr_batch_info": (c_int, [c_void, ctypes.POINTER(c_int), c_int, ctypes.POINTER(c_int)]),
+        "adr_batch_destroy": (c_int, [c_void]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -95,7 +102,8 @@ _lib = _load()
 EXPORTED = ("adr_strerror", "adr_version", "adr_build_1d_ops", "adr_precompute_phi",
             "adr_workspace_bytes", "adr_step", "adr_solve", "adr_mode_product",
             "adr_tucker_workspace_bytes", "adr_tucker", "adr_device_copy",
-            "adr_timing_enable", "adr_timing_read")
+            "adr_timing_enable", "adr_timing_read", "adr_batch_create", "adr_batch_run",
+            "adr_batch_info", "adr_batch_destroy")
 
 
 def _check(status: int, where: str):
@@ -211,6 +219,37 @@ def adr_timing_read(kind: int):
     return launches.value, total.value
 
 
+def adr_batch_create(problems: Sequence[AdrProblem], U, V, works, flags: int = 0, stream=None) -> int:
+    """Build a grouped plan over ``len(problems)`` problems; returns the plan handle."""
+    count = len(problems)
+    if not (len(U) == len(V) == len(works) == count):
+        raise ValueError("problems, U, V and works must have the same length")
+    probs = (AdrProblem * count)(*problems)
+    u = (ctypes.c_void_p * count)(*[_ptr(t) for t in U])
+    v = (ctypes.c_void_p * count)(*[_ptr(t) for t in V])
+    w = (ctypes.c_void_p * count)(*[_ptr(t) for t in works])
+    wb = (ctypes.c_size_t * count)(*[t.numel() * t.element_size() for t in works])
+    plan = ctypes.c_void_p(None)
+    _check(_lib.adr_batch_create(count, probs, u, v, w, wb, int(flags), _stream(stream),
+                                 ctypes.byref(plan)), "adr_batch_create")
+    return plan.value
+
+
+def adr_batch_run(plan: int, nsteps: int, stream=None):
+    _check(_lib.adr_batch_run(plan, int(nsteps), _stream(stream)), "adr_batch_run")
+
+
+def adr_batch_info(plan: int, max_phases: int = 3):
+    cfg = (ctypes.c_int * max(max_phases, 1))()
+    graph = ctypes.c_int(0)
+    _check(_lib.adr_batch_info(plan, cfg, int(max_phases), ctypes.byref(graph)), "adr_batch_info")
+    return list(cfg)[:max_phases], bool(graph.value)
+
+
+def adr_batch_destroy(plan: int):
+    _check(_lib.adr_batch_destroy(plan), "adr_batch_destroy")
+
+
 # ----------------------------------------------------------------------------- problem setup
 
 def to_device_f64(x: np.ndarray, device="cuda") -> torch.Tensor:
@@ -304,5 +343,38 @@ class Solver:
         adr_solve(self.problem, U_dev, V_dev, nsteps, self.work, self.stream)
 
 
+class Batch:
+    """A grouped plan over several workloads (``Solver`` objects hold each
+    problem's operators, matrix functions and workspace; ``states`` their
+    device tensors).  ``run`` advances every problem by ``nsteps`` steps in
+    grouped launches."""
+
+    def __init__(self, solvers: Sequence[Solver], states, flags: int = 0, stream=None):
+        self.solvers = list(solvers)
+        self.states = list(states)
+        self.stream = stream
+        self.plan = adr_batch_create([s.problem for s in self.solvers],
+                                     [u for u, _ in self.states], [v for _, v in self.states],
+                                     [s.work for s in self.solvers], flags, stream)
+
+    def run(self, nsteps: int):
+        adr_batch_run(self.plan, nsteps, self.stream)
+
+    def info(self, max_phases: int = 3):
+        return adr_batch_info(self.plan, max_phases)
+
+    def close(self):
+        if self.plan:
+            adr_batch_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 __all__ = [n for n in dir() if n.startswith(("adr_", "ADR_"))] + [
-    "AdrProblem", "AdrError", "Solver", "to_device_f64", "from_device", "EXPORTED", "LIB_PATH"]
+    "AdrProblem", "AdrError", "Solver", "Batch", "to_device_f64", "from_device", "EXPORTED",
+    "LIB_PATH"]

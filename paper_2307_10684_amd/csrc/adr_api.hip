@@ -8,58 +8,21 @@
 #include <vector>
 
 #include "common.h"
+#include "host_common.h"
 
 using namespace adr;
+using namespace adr::host;
+
+namespace adr {
+namespace host {
+Timing g_timing;
+}  // namespace host
+}  // namespace adr
 
 namespace {
 
-constexpr size_t kAlign = 256;
-inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-// ------------------------------------------------------------------ timing
-struct TimingRec {
-  int kind;
-  int slot;
-};
-struct Timing {
-  int capacity = 0;
-  std::vector<hipEvent_t> pool;  // 2 events per slot
-  std::vector<TimingRec> recs;
-} g_timing;
-
-template <class F>
-hipError_t timed(int kind, hipStream_t s, F&& f) {
-  Timing& t = g_timing;
-  if (t.capacity == 0 || (int)t.recs.size() >= t.capacity) return f();
-  const int slot = (int)t.recs.size();
-  hipError_t e = hipEventRecord(t.pool[2 * slot], s);
-  if (e != hipSuccess) return e;
-  e = f();
-  if (e != hipSuccess) return e;
-  e = hipEventRecord(t.pool[2 * slot + 1], s);
-  if (e != hipSuccess) return e;
-  t.recs.push_back({kind, slot});
-  return hipSuccess;
-}
-constexpr int kKindMode = 0, kKindStage = 1;
-
-inline int dev_err(hipError_t e) { return e == hipSuccess ? ADR_OK : ADR_EDEVICE; }
 
 // ------------------------------------------------------------------ mode products
-struct Geometry {
-  int d;
-  int n[3];
-  long long N;
-};
-
-bool mode_geometry(const Geometry& g, int mu, long long& L, long long& R) {
-  L = 1;
-  R = 1;
-  for (int nu = 0; nu < mu; ++nu) L *= g.n[nu];
-  for (int nu = mu + 1; nu < g.d; ++nu) R *= g.n[nu];
-  return true;
-}
-
 struct TuckerGroup {
   int count = 0;
   const void* in[kMaxGroup] = {};
@@ -78,7 +41,7 @@ struct TuckerGroup {
 // and writes the next direction's fibres contiguous); their intermediates are
 // FP32 and the last product writes the FP64 result in the natural layout.
 hipError_t run_tucker(const Geometry& g, const TuckerGroup& tg, double alpha, double beta,
-                      int precision, hipStream_t s) {
+                      int precision, hipStream_t s, bool last_f32 = false) {
   for (int mu = 0; mu < g.d; ++mu) {
     const bool last = (mu == g.d - 1);
     const void* W[kMaxGroup];
@@ -86,6 +49,7 @@ hipError_t run_tucker(const Geometry& g, const TuckerGroup& tg, double alpha, do
     for (int k = 0; k < tg.count; ++k) {
       W[k] = (mu == 0) ? tg.in[k] : ((mu % 2 == 1) ? tg.t1[k] : tg.t2[k]);
       out[k] = last ? tg.out[k] : ((mu % 2 == 0) ? tg.t1[k] : tg.t2[k]);
+      if (!W[k] || !out[k] || W[k] == out[k]) return hipErrorInvalidValue;
     }
     hipError_t e;
     if (precision == ADR_F64) {
@@ -119,7 +83,8 @@ hipError_t run_tucker(const Geometry& g, const TuckerGroup& tg, double alpha, do
       const long long X = g.N / g.n[mu];
       e = timed(kKindMode, s, [&] {
         return launch_tgemm_lowp(precision, W, Mf, Mh, Ml, out, Y, tg.count, g.n[mu], X,
-                                 last ? alpha : 1.0, last ? beta : 0.0, last ? 1 : 0, s);
+                                 last ? alpha : 1.0, last ? beta : 0.0,
+                                 (last && !last_f32) ? 1 : 0, s);
       });
     }
     if (e != hipSuccess) return e;
@@ -128,7 +93,11 @@ hipError_t run_tucker(const Geometry& g, const TuckerGroup& tg, double alpha, do
 }
 
 // ------------------------------------------------------------------ problem checks
-bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+}  // namespace
+
+namespace adr {
+namespace host {
+static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 int check_problem(const adr_problem* p, Geometry& g) {
   if (!p) return ADR_EINVAL;
@@ -161,20 +130,6 @@ int check_problem(const adr_problem* p, Geometry& g) {
   return ADR_OK;
 }
 
-// Workspace carve-up.  Tensors are FP64 (8 bytes) or FP32 (4 bytes) for the
-// reduced-precision intermediates; reduced-precision modes also hold FP32
-// copies of the small matrices.
-struct Carve {
-  double* U2 = nullptr;
-  double* V2 = nullptr;
-  void* R[4] = {};
-  void* T[4] = {};
-  float* phi32[2][3][3] = {};            // FP32 copies (ADR_F32)
-  unsigned short* phih[2][3][3] = {};    // split-BF16 parts, transposed (ADR_BF16X3)
-  unsigned short* phil[2][3][3] = {};
-  size_t bytes = 0;
-};
-
 Carve carve(const adr_problem* p, const Geometry& g, char* base) {
   Carve c;
   const bool lowp = p->precision != ADR_F64;
@@ -186,11 +141,20 @@ Carve carve(const adr_problem* p, const Geometry& g, char* base) {
     off += b;
     return ptr;
   };
-  c.U2 = static_cast<double*>(take(tb64));
-  c.V2 = static_cast<double*>(take(tb64));
+  if (lowp && p->scheme == ADR_ETD2RKDS) {
+    // FP32 increments of the first Tucker operator replace the FP64 C_{n2}
+    c.D[0] = static_cast<float*>(take(tbw));
+    c.D[1] = static_cast<float*>(take(tbw));
+  } else {
+    c.U2 = static_cast<double*>(take(tb64));
+    c.V2 = static_cast<double*>(take(tb64));
+  }
   const int nin = (p->scheme == ADR_LAWSON2B) ? 4 : 2;
   for (int k = 0; k < nin; ++k) c.R[k] = take(tbw);
-  if (g.d >= 2)
+  // ping buffers of the Tucker chains; the reduced-precision ETD2RKds also
+  // writes its second increment D2 there when d = 1 (it cannot overwrite the
+  // chain's input R)
+  if (g.d >= 2 || (lowp && p->scheme == ADR_ETD2RKDS))
     for (int k = 0; k < nin; ++k) c.T[k] = take(tbw);
   if (lowp) {
     for (int cc = 0; cc < 2; ++cc)
@@ -233,6 +197,11 @@ hipError_t prepare_lowp(const adr_problem* p, const Geometry& g, const Carve& c,
       }
   return hipSuccess;
 }
+
+}  // namespace host
+}  // namespace adr
+
+namespace {
 
 // Small matrices of (component, function j, direction mu) in the form the
 // step's precision consumes.
@@ -299,6 +268,31 @@ hipError_t step_etd2rkds(const adr_problem* p, const Geometry& g, const Carve& c
     tg.t1[cc] = c.T[cc];
     tg.t2[cc] = c.R[cc];
     for (int mu = 0; mu < g.d; ++mu) set_phi(tg, cc, p, c, cc, 1, mu);
+  }
+  if (lowp) {
+    // D1 = tau * Tucker(R1; phi_1) as FP32, the states C_{n2} = C_n + D1 are
+    // formed pointwise in FP64 where they are needed
+    tg.out[0] = c.D[0];
+    tg.out[1] = c.D[1];
+    e = run_tucker(g, tg, p->tau, 0.0, p->precision, s, true);
+    if (e != hipSuccess) return e;
+    e = timed(kKindStage, s, [&] {
+      return launch_etd_stage2_inc(g.N, r, U, V, c.D[0], c.D[1], static_cast<float*>(c.R[0]),
+                                   static_cast<float*>(c.R[1]), s);
+    });
+    if (e != hipSuccess) return e;
+    // D2 = 2^(d-1) tau * Tucker(R2; phi_2) into the buffer the chain does not read last
+    for (int cc = 0; cc < 2; ++cc) {
+      for (int mu = 0; mu < g.d; ++mu) set_phi(tg, cc, p, c, cc, 2, mu);
+      tg.out[cc] = (g.d == 2) ? c.R[cc] : c.T[cc];
+    }
+    e = run_tucker(g, tg, std::ldexp(p->tau, g.d - 1), 0.0, p->precision, s, true);
+    if (e != hipSuccess) return e;
+    const float* D2u = static_cast<const float*>(tg.out[0]);
+    const float* D2v = static_cast<const float*>(tg.out[1]);
+    return timed(kKindStage, s, [&] {
+      return launch_etd_final_inc(g.N, U, V, c.D[0], c.D[1], D2u, D2v, s);
+    });
   }
   tg.out[0] = c.U2;
   tg.out[1] = c.V2;

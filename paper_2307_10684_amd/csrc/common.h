@@ -31,6 +31,29 @@ struct ModeArgs {
   int group;                     // number of tensors in the launch (1..kMaxGroup)
 };
 
+// One product of a grouped launch (also the per-tile view of a single product).
+struct TileJob {
+  const double* W;
+  const double* M;
+  double* out;
+  const double* Y;
+  const double* Z;
+  double alpha, beta, gamma;
+  long long L, X;
+  int n;
+  int n_itiles;
+  long long tile_begin;   // first tile of this job in the grouped launch
+};
+
+// Tile configurations of the FP64 product (rows BI of M x fibres BX per workgroup).
+enum class TileCfg : int { I64X64 = 0, I64X128 = 1, I128X64 = 2, I128X128 = 3 };
+constexpr int kNumTileCfgs = 4;
+void tile_cfg_dims(TileCfg c, int& BI, int& BX);
+// Grouped FP64 products; `jobs` is a device array of `njobs` TileJobs whose tile
+// offsets were laid out for configuration `cfg`; `ntiles` is the total.
+hipError_t launch_mode_grouped_f64(TileCfg cfg, bool kfast, const TileJob* jobs, int njobs,
+                                   long long ntiles, hipStream_t s);
+
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_mode_product_f64(const ModeArgs& a, hipStream_t s);
 
@@ -42,6 +65,21 @@ hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* co
                              const void* const* Mh, const void* const* Ml, void* const* out,
                              const double* const* Y, int group, int n, long long X, double alpha,
                              double beta, int out_f64, hipStream_t s);
+// One FP32 transposing product of a grouped launch (tiles of 128 x 128).
+struct LowpJob {
+  const float* W;
+  const float* M;
+  void* out;
+  const double* Y;
+  double alpha, beta;
+  int n;
+  long long X;
+  int out_f64;
+  int n_itiles;
+  long long tile_begin;
+};
+hipError_t launch_tgemm_lowp_grouped(int precision, const LowpJob* jobs, int njobs,
+                                     long long ntiles, hipStream_t s);
 // Split an FP64 n x n column-major matrix into transposed bf16 hi/lo parts.
 hipError_t launch_split_bf16(int n, const double* M, unsigned short* Mh, unsigned short* Ml,
                              hipStream_t s);
@@ -59,6 +97,35 @@ struct StageGeom {
   const double* band[2][3];   // tridiagonal bands (sub, diag, super) per component/direction, or null
 };
 
+// Grouped stage launches over several problems (batched and serving runs).
+struct StageJob {
+  StageGeom g;
+  Reaction r;
+  const double* U;
+  const double* V;
+  void* R[2];
+  int gx, gy;              // block grid of this problem (x: i1/64, y: i2/4, z: planes)
+  long long block_begin;   // first block of this problem in the grouped launch
+};
+struct PointJob {
+  int kind;                // 0: stage 2, 1: stage 2 from FP32 increments, 2: final C += D1 + D2
+  Reaction r;
+  long long N;
+  const double* U;
+  const double* V;
+  const void* A;           // kind 0: U2 (FP64); kind 1, 2: D1u (FP32)
+  const void* B;           // kind 0: V2; kind 1, 2: D1v
+  const void* C2;          // kind 2: D2u (FP32)
+  const void* D2;          // kind 2: D2v
+  void* R[2];              // kinds 0, 1: outputs
+  long long block_begin;
+};
+hipError_t launch_stage1_grouped(const StageJob* jobs, int njobs, long long nblocks, int r_f32,
+                                 hipStream_t s);
+hipError_t launch_pointwise_grouped(const PointJob* jobs, int njobs, long long nblocks, int r_f32,
+                                    hipStream_t s);
+int stage1_blocks(const StageGeom& g, int& gx, int& gy, int& gz);
+
 // ETD2RKds stage 1: R^c = sum_mu C x_mu A_mu^c (stencil where a band is given,
 // nothing where it is not) + G^c(U, V).  R may be FP64 or FP32.
 hipError_t launch_etd_stage1(const StageGeom& g, const Reaction& r, const double* U,
@@ -67,6 +134,14 @@ hipError_t launch_etd_stage1(const StageGeom& g, const Reaction& r, const double
 hipError_t launch_etd_stage2(long long N, const Reaction& r, const double* U, const double* V,
                              const double* U2, const double* V2, void* Ru, void* Rv, int r_f32,
                              hipStream_t s);
+// Reduced-precision ETD2RKds with FP32 increments D1, D2 of the two Tucker operators:
+// stage 2 R^c = G^c(U + D1u, V + D1v) - G^c(U, V); final C <- C + D1^c + D2^c.
+hipError_t launch_etd_stage2_inc(long long N, const Reaction& r, const double* U, const double* V,
+                                 const float* Du, const float* Dv, float* Ru, float* Rv,
+                                 hipStream_t s);
+hipError_t launch_etd_final_inc(long long N, double* U, double* V, const float* D1u,
+                                const float* D1v, const float* D2u, const float* D2v,
+                                hipStream_t s);
 // Lawson2b stage 1: A^c = C + tau G^c(U, V), B^c = C + tau/2 G^c(U, V).
 hipError_t launch_lawson_stage1(long long N, const Reaction& r, double tau, const double* U,
                                 const double* V, void* Au, void* Av, void* Bu, void* Bv, int f32,

@@ -33,11 +33,16 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 
 constexpr int kPad = 16;  // row padding (doubles): the next k-row lands 32 banks away
 
+// One output tile of a mu-mode product (see ModeArgs for the geometry).  The
+// single-product kernel and the grouped kernel (many products of different
+// shapes in one launch, one TileJob each) both call this.
+//
 // FULL: every tile is complete (n % BI == 0, n % BK == 0, X % BX == 0), so the
 // loads need no bounds predicates and stay in flight across the MFMAs.
-template <int BI, int BX, int WI, int WX, int BK, bool KFAST, bool FULL, int MINB = 2>
-__global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64(ModeArgs a, int n_itiles,
-                                                                int n_xtiles) {
+template <int BI, int BX, int WI, int WX, int BK, bool KFAST, bool FULL>
+__device__ __forceinline__ void mode_tile_f64(const TileJob& job, int itile, int xtile,
+                                              double* __restrict__ sMbase,
+                                              double* __restrict__ sWbase) {
   constexpr int NT = 64 * WI * WX;
   constexpr int TI = BI / WI, TX = BX / WX;  // wave tile
   constexpr int FI = TI / 16, FX = TX / 16;  // 16x16 blocks per wave
@@ -47,6 +52,7 @@ __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64(ModeArgs a, int
   constexpr int LDX = BX + kPad;
   constexpr int LDK = BK + 2;                          // k-fastest rows: conflict-free fragments
   constexpr int SW = KFAST ? BX * LDK : BK * LDX;      // W tile size in LDS
+  constexpr int SM = BK * LDI;
   constexpr int MROWS = NT / BI;                       // k-rows of M loaded per pass
   constexpr int MLOADS = BK / MROWS;                   // doubles per thread
   static_assert(MROWS * BI == NT && MLOADS * MROWS == BK, "M tile mapping");
@@ -55,34 +61,21 @@ __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64(ModeArgs a, int
   constexpr int WLOADS = BX * BK / NT;                 // W doubles per thread
   static_assert(KFAST ? (XSTEP * BK == NT && WLOADS * XSTEP == BX)
                       : (WROWS * BX == NT && WLOADS * WROWS == BK), "W tile mapping");
-
-  __shared__ double sM[2][BK * LDI];
-  __shared__ double sW[2][SW];
+  // double buffers: buffer b of M at sMbase + b*SM, of W at sWbase + b*SW
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wi = wave / WX, wx = wave % WX;
 
-  // Tile index.  The hardware deals workgroups to the 8 XCDs round-robin; give
-  // each XCD a contiguous range of tiles so the i-tiles that re-read the same
-  // W fibres run on the same L2.
-  const int G = gridDim.x;
-  const int b = blockIdx.x;
-  int t = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
-  const int itile = t % n_itiles;
-  t /= n_itiles;
-  const int xtile = t % n_xtiles;
-  const int g = t / n_xtiles;
-
-  const int n = a.n;
-  const unsigned L = (unsigned)a.L;
-  const unsigned X = (unsigned)a.X;
+  const int n = job.n;
+  const unsigned L = (unsigned)job.L;
+  const unsigned X = (unsigned)job.X;
   const unsigned Ln = L * (unsigned)n;
   const int i0 = itile * BI;
   const unsigned x0 = (unsigned)xtile * BX;
-  const double* __restrict__ W = static_cast<const double*>(a.W[g]);
-  const double* __restrict__ M = static_cast<const double*>(a.M[g]);
+  const double* __restrict__ W = job.W;
+  const double* __restrict__ M = job.M;
 
   // ---- per-thread load descriptors ------------------------------------------
   const int m_i = tid % BI;  // M: row i0 + m_i, k-rows m_k0 + p*MROWS
@@ -129,14 +122,14 @@ __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64(ModeArgs a, int
   auto store_chunk = [&](int buf, int k0) {
 #pragma unroll
     for (int p = 0; p < MLOADS; ++p)
-      sM[buf][(m_k0 + p * MROWS) * LDI + m_i] = m_ok(k0, p) ? rm[p] : 0.0;
+      sMbase[buf * SM + (m_k0 + p * MROWS) * LDI + m_i] = m_ok(k0, p) ? rm[p] : 0.0;
 #pragma unroll
     for (int p = 0; p < WLOADS; ++p) {
       const double v = w_okp(k0, p) ? rw[p] : 0.0;
       if (!KFAST)
-        sW[buf][(w_b + p * WROWS) * LDX + w_a] = v;
+        sWbase[buf * SW + (w_b + p * WROWS) * LDX + w_a] = v;
       else
-        sW[buf][(w_b + p * XSTEP) * LDK + w_a] = v;
+        sWbase[buf * SW + (w_b + p * XSTEP) * LDK + w_a] = v;
     }
   };
 
@@ -156,8 +149,8 @@ __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64(ModeArgs a, int
   for (int c = 0; c < nchunks; ++c) {
     const int buf = c & 1;
     if (c + 1 < nchunks) load_chunk((c + 1) * BK);
-    const double* sm = sM[buf];
-    const double* sw = sW[buf];
+    const double* sm = sMbase + buf * SM;
+    const double* sw = sWbase + buf * SW;
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + krow;
@@ -182,10 +175,10 @@ __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64(ModeArgs a, int
 
   // ---- epilogue: out = alpha*acc + beta*Y + gamma*Z --------------------------
   // Y may alias out (each element is read, then written, by the same lane)
-  double* out = static_cast<double*>(a.out[g]);
-  const double* Y = a.Y[g];
-  const double* Z = a.Z[g];
-  const double alpha = a.alpha, beta = a.beta, gamma = a.gamma;
+  double* out = job.out;
+  const double* Y = job.Y;
+  const double* Z = job.Z;
+  const double alpha = job.alpha, beta = job.beta, gamma = job.gamma;
   if (!KFAST) {
 #pragma unroll
     for (int fx = 0; fx < FX; ++fx) {
@@ -228,6 +221,60 @@ __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64(ModeArgs a, int
       }
     }
   }
+}
+
+
+template <int BI, int BX, int WI, int WX, int BK, bool KFAST, bool FULL, int MINB = 2>
+__global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64(ModeArgs a, int n_itiles,
+                                                                int n_xtiles) {
+  constexpr int SW = KFAST ? BX * (BK + 2) : BK * (BX + kPad);
+  __shared__ double sM[2 * BK * (BI + kPad)];
+  __shared__ double sW[2 * SW];
+  // Tile index.  The hardware deals workgroups to the 8 XCDs round-robin; give
+  // each XCD a contiguous range of tiles so the i-tiles that re-read the same
+  // W fibres run on the same L2.
+  const int G = gridDim.x;
+  const int b = blockIdx.x;
+  int t = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  const int itile = t % n_itiles;
+  t /= n_itiles;
+  const int xtile = t % n_xtiles;
+  const int g = t / n_xtiles;
+  TileJob job;
+  job.W = static_cast<const double*>(a.W[g]);
+  job.M = static_cast<const double*>(a.M[g]);
+  job.out = static_cast<double*>(a.out[g]);
+  job.Y = a.Y[g];
+  job.Z = a.Z[g];
+  job.alpha = a.alpha;
+  job.beta = a.beta;
+  job.gamma = a.gamma;
+  job.L = a.L;
+  job.X = a.X;
+  job.n = a.n;
+  mode_tile_f64<BI, BX, WI, WX, BK, KFAST, FULL>(job, itile, xtile, sM, sW);
+}
+
+// Grouped products: job j covers tiles [jobs[j].tile_begin, jobs[j+1].tile_begin)
+// with its own shape, matrix, addend and scalars; a workgroup finds its job by
+// binary search over the sorted tile offsets.
+template <int BI, int BX, int WI, int WX, int BK, bool KFAST>
+__global__ __launch_bounds__(64 * WI * WX, 2) void k_mode_f64_grouped(const TileJob* __restrict__ jobs,
+                                                                     int njobs) {
+  constexpr int SW = KFAST ? BX * (BK + 2) : BK * (BX + kPad);
+  __shared__ double sM[2 * BK * (BI + kPad)];
+  __shared__ double sW[2 * SW];
+  const long long t = blockIdx.x;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+  }
+  const TileJob job = jobs[lo];
+  const long long local = t - job.tile_begin;
+  const int itile = (int)(local % job.n_itiles);
+  const int xtile = (int)(local / job.n_itiles);
+  mode_tile_f64<BI, BX, WI, WX, BK, KFAST, false>(job, itile, xtile, sM, sW);
 }
 
 // Persistent variant for evenly tiled shapes (n % BI == 0, X % BX == 0,
@@ -520,7 +567,40 @@ hipError_t launch_cfg(const ModeArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int BI, int BX, int WI, int WX>
+hipError_t launch_grouped(bool kfast, const TileJob* jobs, int njobs, long long ntiles,
+                          hipStream_t s) {
+  if (njobs <= 0 || ntiles <= 0 || ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
+  constexpr int NT = 64 * WI * WX;
+  if (kfast)
+    hipLaunchKernelGGL((k_mode_f64_grouped<BI, BX, WI, WX, 16, true>), dim3((unsigned)ntiles),
+                       dim3(NT), 0, s, jobs, njobs);
+  else
+    hipLaunchKernelGGL((k_mode_f64_grouped<BI, BX, WI, WX, 16, false>), dim3((unsigned)ntiles),
+                       dim3(NT), 0, s, jobs, njobs);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+void tile_cfg_dims(TileCfg c, int& BI, int& BX) {
+  switch (c) {
+    case TileCfg::I64X64: BI = 64; BX = 64; break;
+    case TileCfg::I64X128: BI = 64; BX = 128; break;
+    case TileCfg::I128X64: BI = 128; BX = 64; break;
+    default: BI = 128; BX = 128; break;
+  }
+}
+
+hipError_t launch_mode_grouped_f64(TileCfg cfg, bool kfast, const TileJob* jobs, int njobs,
+                                   long long ntiles, hipStream_t s) {
+  switch (cfg) {
+    case TileCfg::I64X64: return launch_grouped<64, 64, 2, 2>(kfast, jobs, njobs, ntiles, s);
+    case TileCfg::I64X128: return launch_grouped<64, 128, 1, 4>(kfast, jobs, njobs, ntiles, s);
+    case TileCfg::I128X64: return launch_grouped<128, 64, 2, 2>(kfast, jobs, njobs, ntiles, s);
+    default: return launch_grouped<128, 128, 2, 2>(kfast, jobs, njobs, ntiles, s);
+  }
+}
 
 hipError_t launch_mode_product_f64(const ModeArgs& a, hipStream_t s) {
   hipError_t e = hipSuccess;

@@ -53,16 +53,33 @@ struct LowpArgs {
 
 constexpr int kThreads = 256;
 
+// the product g of a single launch as a job
+__device__ __forceinline__ LowpJob job_of(const LowpArgs& a, int g) {
+  LowpJob j;
+  j.W = a.W[g];
+  j.M = a.M[g];
+  j.out = a.out[g];
+  j.Y = a.Y[g];
+  j.alpha = a.alpha;
+  j.beta = a.beta;
+  j.n = a.n;
+  j.X = a.X;
+  j.out_f64 = 0;
+  j.n_itiles = 0;
+  j.tile_begin = 0;
+  return j;
+}
+
 // Epilogue of a wave's TI x TX block of D[i][x] (lane: rows 4*krow + v of each
 // 16x16 block, column col).  For the FP64 output all addends of one 16-column
 // strip are loaded before any result is formed, so their latencies overlap.
 template <int FI, int FX, int TI, int TX, bool OUT64>
-__device__ __forceinline__ void tgemm_epilogue(const LowpArgs& a, int g, const f4 (&acc)[FI][FX],
+__device__ __forceinline__ void tgemm_epilogue(const LowpJob& a, const f4 (&acc)[FI][FX],
                                                int ib, unsigned xb, int col, int krow) {
   const int n = a.n;
-  const unsigned X = a.X;
+  const unsigned X = (unsigned)a.X;
   const double alpha = a.alpha, beta = a.beta;
-  const double* Y = a.Y[g];
+  const double* Y = a.Y;
 #pragma unroll
   for (int fx = 0; fx < FX; ++fx) {
     const unsigned x = xb + fx * 16 + col;
@@ -77,7 +94,7 @@ __device__ __forceinline__ void tgemm_epilogue(const LowpArgs& a, int g, const f
           const bool ok = xok && i < n && Y != nullptr;
           y[fi][v] = ok ? Y[x + X * (unsigned)i] : 0.0;
         }
-      double* out = static_cast<double*>(a.out[g]);
+      double* out = static_cast<double*>(a.out);
 #pragma unroll
       for (int fi = 0; fi < FI; ++fi)
 #pragma unroll
@@ -86,7 +103,7 @@ __device__ __forceinline__ void tgemm_epilogue(const LowpArgs& a, int g, const f
           if (xok && i < n) out[x + X * (unsigned)i] = alpha * (double)acc[fi][fx][v] + beta * y[fi][v];
         }
     } else {
-      float* out = static_cast<float*>(a.out[g]);
+      float* out = static_cast<float*>(a.out);
 #pragma unroll
       for (int fi = 0; fi < FI; ++fi)
 #pragma unroll
@@ -100,9 +117,10 @@ __device__ __forceinline__ void tgemm_epilogue(const LowpArgs& a, int g, const f
 
 // ------------------------------------------------------------------ FP32
 // Tile: BI rows i x BX fibres x, BK = 16 per chunk, four waves in a 2x2 grid.
+// The single-launch kernel and the grouped kernel (one LowpJob per product)
+// both call this.
 template <int BI, int BX, bool OUT64>
-__global__ __launch_bounds__(kThreads, 2) void k_tgemm_f32(LowpArgs a, int n_itiles,
-                                                          int n_xtiles) {
+__device__ __forceinline__ void tgemm_f32_tile(const LowpJob& job, int itile, int xtile) {
   constexpr int BK = 16;
   constexpr int WI = 2, WX = 2;
   constexpr int TI = BI / WI, TX = BX / WX, FI = TI / 16, FX = TX / 16;
@@ -116,18 +134,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_tgemm_f32(LowpArgs a, int n_iti
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = wave / WX, wx = wave % WX;
-  const int G = gridDim.x, b = blockIdx.x;
-  int t = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
-  const int itile = t % n_itiles;
-  t /= n_itiles;
-  const int xtile = t % n_xtiles;
-  const int g = t / n_xtiles;
-  const int n = a.n;
-  const unsigned X = a.X;
+  const int n = job.n;
+  const unsigned X = (unsigned)job.X;
   const int i0 = itile * BI;
   const unsigned x0 = (unsigned)xtile * BX;
-  const float* __restrict__ W = a.W[g];
-  const float* __restrict__ M = a.M[g];
+  const float* __restrict__ W = job.W;
+  const float* __restrict__ M = job.M;
 
   const int m_i = tid % BI, m_k0 = tid / BI;
   const int w_k = tid % BK, w_x0 = tid / BK;
@@ -191,7 +203,35 @@ __global__ __launch_bounds__(kThreads, 2) void k_tgemm_f32(LowpArgs a, int n_iti
     __syncthreads();
   }
   // D[i][x]: lane holds rows i = 4*krow + v, column x = col
-  tgemm_epilogue<FI, FX, TI, TX, OUT64>(a, g, acc, i0 + wi * TI, x0 + wx * TX, col, krow);
+  tgemm_epilogue<FI, FX, TI, TX, OUT64>(job, acc, i0 + wi * TI, x0 + wx * TX, col, krow);
+}
+
+template <int BI, int BX, bool OUT64>
+__global__ __launch_bounds__(kThreads, 2) void k_tgemm_f32(LowpArgs a, int n_itiles,
+                                                          int n_xtiles) {
+  const int G = gridDim.x, b = blockIdx.x;
+  int t = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  const int itile = t % n_itiles;
+  t /= n_itiles;
+  const int xtile = t % n_xtiles;
+  const int g = t / n_xtiles;
+  tgemm_f32_tile<BI, BX, OUT64>(job_of(a, g), itile, xtile);
+}
+
+// Grouped FP32 products with FP32 outputs (one LowpJob per product, binary
+// search over the sorted tile offsets).
+template <int BI, int BX>
+__global__ __launch_bounds__(kThreads, 2) void k_tgemm_f32_grouped(const LowpJob* __restrict__ jobs,
+                                                                  int njobs) {
+  const long long t = blockIdx.x;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+  }
+  const LowpJob job = jobs[lo];
+  const long long local = t - job.tile_begin;
+  tgemm_f32_tile<BI, BX, false>(job, (int)(local % job.n_itiles), (int)(local / job.n_itiles));
 }
 
 // ------------------------------------------------------------------ split BF16
@@ -332,7 +372,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_tgemm_bf16x3(LowpArgs a, int n_
     if (c + 1 < nchunks) store(buf ^ 1);
     __syncthreads();
   }
-  tgemm_epilogue<FI, FX, TI, TX, OUT64>(a, g, acc, i0 + wi * TI, x0 + wx * TX, col, kq);
+  tgemm_epilogue<FI, FX, TI, TX, OUT64>(job_of(a, g), acc, i0 + wi * TI, x0 + wx * TX, col, kq);
 }
 
 // Split an FP64 n x n column-major matrix into transposed bf16 hi/lo parts:
@@ -411,6 +451,15 @@ hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* co
                    : launch_tiles(k_tgemm_bf16x3<128, 128, false, true>, a, 128, 128, s);
   return out_f64 ? launch_tiles(k_tgemm_bf16x3<128, 128, true, false>, a, 128, 128, s)
                  : launch_tiles(k_tgemm_bf16x3<128, 128, false, false>, a, 128, 128, s);
+}
+
+hipError_t launch_tgemm_lowp_grouped(int precision, const LowpJob* jobs, int njobs,
+                                     long long ntiles, hipStream_t s) {
+  if (precision != 1 || njobs <= 0 || ntiles <= 0 || ntiles > 0x7fffffffLL)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_tgemm_f32_grouped<128, 128>), dim3((unsigned)ntiles), dim3(kThreads), 0, s,
+                     jobs, njobs);
+  return hipGetLastError();
 }
 
 hipError_t launch_split_bf16(int n, const double* M, unsigned short* Mh, unsigned short* Ml,

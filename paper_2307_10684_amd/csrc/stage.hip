@@ -52,16 +52,16 @@ __device__ __forceinline__ void put(void* p, long long q, double x) {
 constexpr int kZB = 16;  // planes per block
 
 template <typename TR>
-__global__ __launch_bounds__(256) void k_etd_stage1(StageGeom g, Reaction r,
-                                                    const double* __restrict__ U,
-                                                    const double* __restrict__ V, void* Ru,
-                                                    void* Rv) {
+__device__ __forceinline__ void etd_stage1_block(const StageGeom& g, const Reaction& r,
+                                                 const double* __restrict__ U,
+                                                 const double* __restrict__ V, void* Ru,
+                                                 void* Rv, int bx, int by, int bz) {
   const int n1 = g.n[0], n2 = g.d >= 2 ? g.n[1] : 1, n3 = g.d >= 3 ? g.n[2] : 1;
-  const int i1 = blockIdx.x * 64 + threadIdx.x;
+  const int i1 = bx * 64 + threadIdx.x;
   // i_2 is the same on the whole wave (blockDim.x = 64): keep it in a scalar
   // register so its band coefficients are scalar loads
-  const int i2 = __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + threadIdx.y);
-  const int z0 = blockIdx.z * kZB;
+  const int i2 = __builtin_amdgcn_readfirstlane(by * 4 + threadIdx.y);
+  const int z0 = bz * kZB;
   const int z1 = min(z0 + kZB, n3);
   const bool live = i1 < n1 && i2 < n2;
   const unsigned P = (unsigned)n1 * (unsigned)n2;  // plane stride
@@ -146,6 +146,69 @@ __global__ __launch_bounds__(256) void k_etd_stage1(StageGeom g, Reaction r,
   }
 }
 
+template <typename TR>
+__global__ __launch_bounds__(256) void k_etd_stage1(StageGeom g, Reaction r,
+                                                    const double* __restrict__ U,
+                                                    const double* __restrict__ V, void* Ru,
+                                                    void* Rv) {
+  etd_stage1_block<TR>(g, r, U, V, Ru, Rv, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Grouped stage 1 over several problems: job j owns blocks
+// [jobs[j].block_begin, jobs[j+1].block_begin), laid out as gx * gy * gz.
+template <typename TR>
+__global__ __launch_bounds__(256) void k_etd_stage1_grouped(const StageJob* __restrict__ jobs,
+                                                            int njobs) {
+  const long long b = blockIdx.x;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].block_begin <= b) lo = mid; else hi = mid - 1;
+  }
+  const StageJob& j = jobs[lo];
+  const int local = (int)(b - j.block_begin);
+  const int bx = local % j.gx, rest = local / j.gx;
+  etd_stage1_block<TR>(j.g, j.r, j.U, j.V, j.R[0], j.R[1], bx, rest % j.gy, rest / j.gy);
+}
+
+// Grouped pointwise stages: job j owns blocks [block_begin, next block_begin) of
+// 256 points each over its N points; kind 0 = ETD2RKds stage 2 (FP64 states
+// A = U2, B = V2), kind 1 = stage 2 from FP32 increments (A = D1u, B = D1v),
+// kind 2 = final C += D1 + D2 (A, B = D1, C2, D2 = D2).
+template <typename TR>
+__global__ __launch_bounds__(256) void k_pointwise_grouped(const PointJob* __restrict__ jobs,
+                                                           int njobs) {
+  const long long b = blockIdx.x;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].block_begin <= b) lo = mid; else hi = mid - 1;
+  }
+  const PointJob& j = jobs[lo];
+  const long long q = (b - j.block_begin) * 256 + threadIdx.x;
+  if (q >= j.N) return;
+  if (j.kind == 0) {
+    double gu, gv, gu2, gv2;
+    react(j.r, j.U[q], j.V[q], gu, gv);
+    react(j.r, static_cast<const double*>(j.A)[q], static_cast<const double*>(j.B)[q], gu2, gv2);
+    put<TR>(j.R[0], q, gu2 - gu);
+    put<TR>(j.R[1], q, gv2 - gv);
+  } else if (j.kind == 1) {
+    const double u = j.U[q], v = j.V[q];
+    double gu, gv, gu2, gv2;
+    react(j.r, u, v, gu, gv);
+    react(j.r, u + (double)static_cast<const float*>(j.A)[q],
+          v + (double)static_cast<const float*>(j.B)[q], gu2, gv2);
+    put<TR>(j.R[0], q, gu2 - gu);
+    put<TR>(j.R[1], q, gv2 - gv);
+  } else {
+    double* U = const_cast<double*>(j.U);
+    double* V = const_cast<double*>(j.V);
+    U[q] = (U[q] + (double)static_cast<const float*>(j.A)[q]) + (double)static_cast<const float*>(j.C2)[q];
+    V[q] = (V[q] + (double)static_cast<const float*>(j.B)[q]) + (double)static_cast<const float*>(j.D2)[q];
+  }
+}
+
 // Stage 2: R^c = G^c(U2, V2) - G^c(U, V).
 template <typename TR>
 __global__ __launch_bounds__(256) void k_etd_stage2(long long N, Reaction r,
@@ -161,6 +224,41 @@ __global__ __launch_bounds__(256) void k_etd_stage2(long long N, Reaction r,
     react(r, U2[q], V2[q], gu2, gv2);
     put<TR>(Ru, q, gu2 - gu);
     put<TR>(Rv, q, gv2 - gv);
+  }
+}
+
+// Reduced-precision ETD2RKds keeps the Tucker results as FP32 increments
+// D1 = tau T1, D2 = 2^(d-1) tau T2 and forms the FP64 states pointwise:
+// stage 2: R^c = G^c(U + D1u, V + D1v) - G^c(U, V);
+// final:   C <- C + D1^c + D2^c   (i.e. C_{n+1} = C_{n2} + D2 with C_{n2} = C_n + D1).
+__global__ __launch_bounds__(256) void k_etd_stage2_inc(long long N, Reaction r,
+                                                        const double* __restrict__ U,
+                                                        const double* __restrict__ V,
+                                                        const float* __restrict__ Du,
+                                                        const float* __restrict__ Dv,
+                                                        float* __restrict__ Ru,
+                                                        float* __restrict__ Rv) {
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
+       q += (long long)gridDim.x * blockDim.x) {
+    const double u = U[q], v = V[q];
+    double gu, gv, gu2, gv2;
+    react(r, u, v, gu, gv);
+    react(r, u + (double)Du[q], v + (double)Dv[q], gu2, gv2);
+    Ru[q] = (float)(gu2 - gu);
+    Rv[q] = (float)(gv2 - gv);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_etd_final_inc(long long N, double* __restrict__ U,
+                                                       double* __restrict__ V,
+                                                       const float* __restrict__ D1u,
+                                                       const float* __restrict__ D1v,
+                                                       const float* __restrict__ D2u,
+                                                       const float* __restrict__ D2v) {
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
+       q += (long long)gridDim.x * blockDim.x) {
+    U[q] = (U[q] + (double)D1u[q]) + (double)D2u[q];
+    V[q] = (V[q] + (double)D1v[q]) + (double)D2v[q];
   }
 }
 
@@ -247,6 +345,22 @@ hipError_t launch_etd_stage2(long long N, const Reaction& r, const double* U, co
   return hipGetLastError();
 }
 
+hipError_t launch_etd_stage2_inc(long long N, const Reaction& r, const double* U, const double* V,
+                                 const float* Du, const float* Dv, float* Ru, float* Rv,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_etd_stage2_inc, dim3(stream_grid(N)), dim3(256), 0, s, N, r, U, V, Du, Dv,
+                     Ru, Rv);
+  return hipGetLastError();
+}
+
+hipError_t launch_etd_final_inc(long long N, double* U, double* V, const float* D1u,
+                                const float* D1v, const float* D2u, const float* D2v,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_etd_final_inc, dim3(stream_grid(N)), dim3(256), 0, s, N, U, V, D1u, D1v,
+                     D2u, D2v);
+  return hipGetLastError();
+}
+
 hipError_t launch_lawson_stage1(long long N, const Reaction& r, double tau, const double* U,
                                 const double* V, void* Au, void* Av, void* Bu, void* Bv, int f32,
                                 hipStream_t s) {
@@ -263,6 +377,35 @@ hipError_t launch_lawson_stage2(long long N, const Reaction& r, double tau, doub
                                 const double* U2, const double* V2, hipStream_t s) {
   hipLaunchKernelGGL(k_law_stage2, dim3(stream_grid(N)), dim3(256), 0, s, N, r, tau, U, V, U2, V2);
   return hipGetLastError();
+}
+
+hipError_t launch_stage1_grouped(const StageJob* jobs, int njobs, long long nblocks, int r_f32,
+                                 hipStream_t s) {
+  if (njobs <= 0 || nblocks <= 0 || nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 block(64, 4);
+  if (r_f32)
+    hipLaunchKernelGGL(k_etd_stage1_grouped<float>, dim3((unsigned)nblocks), block, 0, s, jobs, njobs);
+  else
+    hipLaunchKernelGGL(k_etd_stage1_grouped<double>, dim3((unsigned)nblocks), block, 0, s, jobs, njobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_pointwise_grouped(const PointJob* jobs, int njobs, long long nblocks, int r_f32,
+                                    hipStream_t s) {
+  if (njobs <= 0 || nblocks <= 0 || nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  if (r_f32)
+    hipLaunchKernelGGL(k_pointwise_grouped<float>, dim3((unsigned)nblocks), dim3(256), 0, s, jobs, njobs);
+  else
+    hipLaunchKernelGGL(k_pointwise_grouped<double>, dim3((unsigned)nblocks), dim3(256), 0, s, jobs, njobs);
+  return hipGetLastError();
+}
+
+int stage1_blocks(const StageGeom& g, int& gx, int& gy, int& gz) {
+  const int n2 = g.d >= 2 ? g.n[1] : 1, n3 = g.d >= 3 ? g.n[2] : 1;
+  gx = (g.n[0] + 63) / 64;
+  gy = (n2 + 3) / 4;
+  gz = (n3 + kZB - 1) / kZB;
+  return gx * gy * gz;
 }
 
 hipError_t launch_copy_f64(const double* in, double* out, size_t count, hipStream_t s) {

@@ -146,3 +146,46 @@ def test_strerror_covers_all_codes(adr):
     texts = {adr.adr_strerror(s) for s in (0, -1, -2, -3, -4, -5)}
     assert len(texts) == 6
     assert adr.adr_strerror(-99) == "unknown status"
+
+
+def _batch_create(adr, probs, work=4096, work_bytes=1 << 30, flags=0, U=4096):
+    lib = adr._lib
+    count = len(probs)
+    arr = (adr.AdrProblem * max(count, 1))(*probs)
+    ptrs = lambda v: (ctypes.c_void_p * max(count, 1))(*([v] * max(count, 1)))
+    sizes = (ctypes.c_size_t * max(count, 1))(*([work_bytes] * max(count, 1)))
+    plan = ctypes.c_void_p(None)
+    st = lib.adr_batch_create(count, arr, ptrs(U), ptrs(4096), ptrs(work), sizes, flags, None,
+                              ctypes.byref(plan))
+    assert plan.value is None  # no plan on failure
+    return st
+
+
+def test_batch_create_validates_before_device_work(adr):
+    ok = _problem(adr)
+    assert _batch_create(adr, []) == adr.ADR_EINVAL
+    assert _batch_create(adr, [ok], flags=8) == adr.ADR_EINVAL
+    assert _batch_create(adr, [ok], U=None) == adr.ADR_EINVAL
+    assert _batch_create(adr, [ok], work=4097) == adr.ADR_EINVAL
+    assert _batch_create(adr, [ok, ok], work_bytes=64) == adr.ADR_ENOMEM
+    bad = _problem(adr)
+    bad.tau = 0.0
+    assert _batch_create(adr, [ok, bad]) == adr.ADR_EINVAL
+    law = _problem(adr)
+    law.scheme = adr.ADR_LAWSON2B
+    assert _batch_create(adr, [ok, law]) == adr.ADR_ENOTSUP
+    f32 = _problem(adr)
+    f32.precision = adr.ADR_F32
+    assert _batch_create(adr, [ok, f32]) == adr.ADR_ENOTSUP   # mixed precisions
+    b3 = _problem(adr)
+    b3.precision = adr.ADR_BF16X3
+    assert _batch_create(adr, [b3]) == adr.ADR_ENOTSUP
+    dense = _problem(adr)
+    dense.band[1][2] = None
+    dense.dense[1][2] = 4096
+    assert _batch_create(adr, [dense]) == adr.ADR_ENOTSUP
+    lib = adr._lib
+    assert lib.adr_batch_run(None, 1, None) == adr.ADR_EINVAL
+    assert lib.adr_batch_info(None, None, 0, None) == adr.ADR_EINVAL
+    assert lib.adr_batch_destroy(None) == adr.ADR_EINVAL
+    assert lib.adr_batch_create(1, None, None, None, None, None, 0, None, None) == adr.ADR_EINVAL

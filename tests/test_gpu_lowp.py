@@ -24,6 +24,7 @@ CASES = [
     ("schnak2d_64_100", S.schnakenberg_2d(64, 100), 100),
     ("fhn3d_48_50", S.fhn_3d(48, 50), 50),
     ("schnak2d_130x70_20", S.with_shape(S.schnakenberg_2d(), (130, 70)), 20),
+    ("bruss1d_300_50", S.with_shape(S.brusselator_3d(), (300,)), 50),
 ]
 
 
