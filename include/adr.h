@@ -200,17 +200,28 @@ int adr_device_copy(const double* in, double* out, size_t count, void* stream);
  *               product phase on the plan's own buffers and keep the fastest
  *               (cached per phase shape for the process; with the environment
  *               variable ADR_TUNE_CACHE naming a file, also across processes).
+ *               The cache key is the phase's precision, direction, largest
+ *               n_mu, product count and log2 of its multiply-adds.
  *               Tuning launches write only workspace, never U or V.
  *               ADR_BATCH_GRAPH: capture one step in a HIP graph that
  *               adr_batch_run replays.
- *   stream      stream for the set-up work (FP32 matrix copies, tuning)
+ *               ADR_BATCH_PREPARED (ADR_F32): the FP32 copies of the small
+ *               matrices that a plan keeps in each workspace are already there
+ *               (an earlier plan over the same problem and workspace wrote
+ *               them); skip rewriting them.
+ *   stream      stream for the set-up work (table upload, FP32 matrix copies,
+ *               tuning); synchronised before the call returns, so plans can be
+ *               built on a side stream while other plans run elsewhere
  *   plan        receives the plan
+ * The plan's device tables come from a pool that destroyed plans return to
+ * (no device-wide synchronisation on destroy).  A plan may be destroyed once
+ * no run of it is pending on any stream.
  * Errors: ADR_EINVAL, ADR_ENOMEM (a workspace too small, or no device memory
  * for the tables), ADR_ENOTSUP (scheme, precision or a missing band),
  * ADR_EDEVICE.
  */
 typedef struct adr_batch adr_batch;
-enum adr_batch_flags { ADR_BATCH_AUTOTUNE = 1, ADR_BATCH_GRAPH = 2 };
+enum adr_batch_flags { ADR_BATCH_AUTOTUNE = 1, ADR_BATCH_GRAPH = 2, ADR_BATCH_PREPARED = 4 };
 int adr_batch_create(int count, const adr_problem* problems, double* const* U,
                      double* const* V, void* const* work, const size_t* work_bytes, int flags,
                      void* stream, adr_batch** plan);

@@ -27,7 +27,7 @@ ADR_BC_NEUMANN = 0
 ADR_ETD2RKDS, ADR_LAWSON2B = 0, 1
 ADR_F64, ADR_F32, ADR_BF16X3 = 0, 1, 2
 ADR_SCHNAKENBERG, ADR_FHN, ADR_BRUSSELATOR, ADR_ZERO = 0, 1, 2, 3
-ADR_BATCH_AUTOTUNE, ADR_BATCH_GRAPH = 1, 2
+ADR_BATCH_AUTOTUNE, ADR_BATCH_GRAPH, ADR_BATCH_PREPARED = 1, 2, 4
 
 MODEL_IDS = {"schnakenberg": ADR_SCHNAKENBERG, "fhn": ADR_FHN,
              "brusselator": ADR_BRUSSELATOR, "zero": ADR_ZERO}
@@ -248,6 +248,29 @@ def adr_batch_info(plan: int, max_phases: int = 3):
 
 def adr_batch_destroy(plan: int):
     _check(_lib.adr_batch_destroy(plan), "adr_batch_destroy")
+
+
+def workspace_bytes_for(n: Sequence[int], precision: str = "f64", scheme: str = "etd2rkds") -> int:
+    """adr_workspace_bytes for a grid, before any device buffer exists (the size
+    depends only on the grid, scheme and precision; the pointers are placeholders
+    that the call checks for presence only)."""
+    p = AdrProblem()
+    p.d = len(n)
+    for mu in range(3):
+        p.n[mu] = int(n[mu]) if mu < p.d else 1
+    p.model = ADR_ZERO
+    p.scheme = SCHEME_IDS[scheme]
+    p.precision = PRECISION_IDS[precision]
+    p.tau = 1.0
+    for c in range(2):
+        for mu in range(p.d):
+            for j in range(3):
+                p.phi[c][j][mu] = 256
+            p.band[c][mu] = 256
+    nbytes = adr_workspace_bytes(p)
+    if nbytes == 0:
+        raise AdrError(ADR_EINVAL, "adr_workspace_bytes")
+    return nbytes
 
 
 # ----------------------------------------------------------------------------- problem setup

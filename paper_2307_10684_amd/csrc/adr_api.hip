@@ -5,6 +5,8 @@
 
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -399,6 +401,16 @@ hipError_t gemm(int n, const double* A, const double* B, double* C, double alpha
 
 // ====================================================================== ABI
 
+// scratch of adr_precompute_phi, per device
+namespace {
+struct PhiScratch {
+  void* ptr = nullptr;
+  size_t cap = 0;
+};
+std::mutex g_phi_mu;
+std::map<int, PhiScratch> g_phi_scratch;
+}  // namespace
+
 extern "C" {
 
 const char* adr_strerror(int status) {
@@ -461,8 +473,25 @@ int adr_precompute_phi(int n, const double* A_dev, double tau, double* E_dev, do
   const size_t nn = (size_t)n * n;
   // buffers: Y^1..Y^6, block B, Horner H, current E/P1/P2, next E/P1/P2, norm
   constexpr int kBuf = 14;
-  double* base = nullptr;
-  if (hipMalloc(&base, sizeof(double) * (nn * kBuf + 1)) != hipSuccess) return ADR_ENOMEM;
+  // The scratch is a per-device block that grows and is kept (the call ends
+  // with a synchronisation of `s`, so the next call can reuse it).  Freeing
+  // it would wait for the whole device, stalling unrelated streams.
+  std::lock_guard<std::mutex> lock(g_phi_mu);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ADR_EDEVICE;
+  PhiScratch& sc = g_phi_scratch[dev];
+  const size_t need = sizeof(double) * (nn * kBuf + 1);
+  if (sc.cap < need) {
+    if (sc.ptr) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(sc.ptr);
+      sc.ptr = nullptr;
+      sc.cap = 0;
+    }
+    if (hipMalloc(&sc.ptr, need) != hipSuccess) return ADR_ENOMEM;
+    sc.cap = need;
+  }
+  double* base = static_cast<double*>(sc.ptr);
   double* Yp[7];
   for (int j = 1; j <= 6; ++j) Yp[j] = base + nn * (j - 1);
   double* Bb = base + nn * 6;
@@ -473,7 +502,6 @@ int adr_precompute_phi(int n, const double* A_dev, double tau, double* E_dev, do
   int status = ADR_OK;
   auto fail = [&](int st) {
     (void)hipStreamSynchronize(s);
-    (void)hipFree(base);
     return st;
   };
   // ||tau A||_1 sets the scaling power s with ||tau A / 2^s||_1 <= 1
@@ -536,7 +564,6 @@ int adr_precompute_phi(int n, const double* A_dev, double tau, double* E_dev, do
     if (outs[j]) e = launch_copy_f64(cur[j], outs[j], nn, s);
   if (e != hipSuccess) return fail(ADR_EDEVICE);
   if (hipStreamSynchronize(s) != hipSuccess) status = ADR_EDEVICE;
-  (void)hipFree(base);
   return status;
 }
 

@@ -8,6 +8,7 @@
 // replayed.  Tile shapes of the grouped mode products are chosen per phase by
 // timing the candidates on the plan's own data (cached per phase signature).
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -39,6 +40,39 @@ struct ModePhase {
   TileCfg cfg = TileCfg::I128X128;
   std::string signature;
 };
+
+// Device memory of plan tables is pooled: destroying a plan returns its block
+// here instead of calling hipFree (which waits for the whole device), so plans
+// can be rebuilt while other work runs.  Blocks live until the process ends.
+std::mutex g_pool_mu;
+std::multimap<size_t, char*> g_pool;  // capacity -> free block
+std::map<char*, size_t> g_cap;        // every block -> its capacity
+
+char* pool_take(size_t bytes) {
+  {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    auto it = g_pool.lower_bound(bytes);
+    if (it != g_pool.end() && it->first <= 4 * bytes + 65536) {
+      char* p = it->second;
+      g_pool.erase(it);
+      return p;
+    }
+  }
+  // round up so that blocks are reusable by plans of similar size
+  size_t cap = 65536;
+  while (cap < bytes) cap *= 2;
+  char* p = nullptr;
+  if (hipMalloc(&p, cap) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  g_cap[p] = cap;
+  return p;
+}
+
+void pool_give(char* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  g_pool.emplace(g_cap[p], p);
+}
 
 // autotune cache: phase signature -> chosen configuration
 std::mutex g_tune_mu;
@@ -153,16 +187,22 @@ Chain chain_of(const adr_batch& b, int i, int c, int t) {
   return ch;
 }
 
+// Autotune key of a mode-product phase: precision, direction, largest n_mu,
+// number of products, and the phase's multiply-adds rounded to a power of two.
+// Plans with similar mixes (as a serving loop builds them) share a decision.
 std::string phase_signature(const adr_batch& b, int mu) {
-  std::ostringstream os;
-  os << "p" << b.precision << "_mu" << mu;
+  int nmax = 0, jobs = 0;
+  double macs = 0.0;
   for (int i = 0; i < b.count; ++i) {
     const Geometry& g = b.geoms[i];
     if (mu >= g.d) continue;
-    long long L, R;
-    mode_geometry(g, mu, L, R);
-    os << "_" << g.n[mu] << "x" << L << "x" << R;
+    nmax = std::max(nmax, g.n[mu]);
+    jobs += 2;
+    macs += 2.0 * (double)g.n[mu] * (double)g.N;
   }
+  std::ostringstream os;
+  os << "p" << b.precision << "_mu" << mu << "_n" << nmax << "_j" << jobs << "_m"
+     << (macs > 0 ? (int)std::lround(std::log2(macs)) : 0);
   return os.str();
 }
 
@@ -214,7 +254,7 @@ void destroy(adr_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);
-  if (b->dev) (void)hipFree(b->dev);
+  pool_give(b->dev);
   delete b;
 }
 
@@ -227,7 +267,7 @@ int adr_batch_create(int count, const adr_problem* problems, double* const* U, d
                      adr_batch** plan) {
   if (!plan) return ADR_EINVAL;
   *plan = nullptr;
-  if (flags & ~(ADR_BATCH_AUTOTUNE | ADR_BATCH_GRAPH)) return ADR_EINVAL;
+  if (flags & ~(ADR_BATCH_AUTOTUNE | ADR_BATCH_GRAPH | ADR_BATCH_PREPARED)) return ADR_EINVAL;
   std::vector<Geometry> geoms;
   int st = validate(count, problems, U, V, work, work_bytes, geoms);
   if (st != ADR_OK) return st;
@@ -384,7 +424,8 @@ int adr_batch_create(int count, const adr_problem* problems, double* const* U, d
       for (int k = 0; k < kNumTileCfgs; ++k) o_mode[t][mu][k] = reserve(sizeof(TileJob) * tj[t][mu][k].size() + 1);
       o_low[t][mu] = reserve(sizeof(LowpJob) * lj[t][mu].size() + 1);
     }
-  if (hipMalloc(&b->dev, bytes) != hipSuccess) {
+  b->dev = pool_take(bytes);
+  if (!b->dev) {
     destroy(b);
     return ADR_ENOMEM;
   }
@@ -407,12 +448,12 @@ int adr_batch_create(int count, const adr_problem* problems, double* const* U, d
         std::memcpy(host.data() + o_low[t][mu], lj[t][mu].data(), sizeof(LowpJob) * lj[t][mu].size());
       m.ljobs = reinterpret_cast<LowpJob*>(b->dev + o_low[t][mu]);
     }
-  if (hipMemcpy(b->dev, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+  if (hipMemcpyAsync(b->dev, host.data(), bytes, hipMemcpyHostToDevice, s) != hipSuccess) {
     destroy(b);
     return ADR_EDEVICE;
   }
   // reduced precision: FP32 copies of the small matrices (they do not change)
-  for (int i = 0; i < count && lowp; ++i)
+  for (int i = 0; i < count && lowp && !(flags & ADR_BATCH_PREPARED); ++i)
     if (prepare_lowp(&b->probs[i], geoms[i], b->carves[i], s) != hipSuccess) {
       destroy(b);
       return ADR_EDEVICE;
@@ -451,10 +492,15 @@ int adr_batch_create(int count, const adr_problem* problems, double* const* U, d
     b->autotuned = true;
   }
 
+  // the tables (from a host vector) and the matrix copies are complete on return
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    destroy(b);
+    return ADR_EDEVICE;
+  }
+
   // ---- capture one step in a graph
   if (flags & ADR_BATCH_GRAPH) {
-    if (hipStreamSynchronize(s) != hipSuccess ||
-        hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
       destroy(b);
       return ADR_EDEVICE;
     }

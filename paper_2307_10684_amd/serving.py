@@ -1,0 +1,372 @@
+"""Continuous-batching serving loop for ETD2RKds solves on one GPU.
+
+Requests (a grid, a reaction model, a step size, a step count and initial
+data) arrive over time.  The engine admits them by an HBM budget and a slot
+limit, keeps each admitted solve's state tensors, operators and matrix
+functions resident on the device, and advances every admitted solve together:
+one grouped plan (``adr_batch_*``) steps all of them in ``2*d_max + 2``
+launches per step, so the work of different requests overlaps inside the same
+kernels.  The loop runs in rounds of at most ``max_chunk`` steps; a round
+never takes a request past its step count, and a finished request's state is
+copied back while the next round already runs.  Rounds are pipelined
+``depth`` deep: while the device works on round k, the host admits new
+arrivals (building their operators and matrix functions on a side stream) and
+queues round k+1 with a plan that includes them.
+
+The engine is pure scheduling logic.  The device work goes through a backend
+object; ``GpuBackend`` below drives the HIP library, and the tests drive the
+same engine with a CPU stand-in.
+
+Backend protocol::
+
+    footprint(job) -> int          device bytes the request holds while admitted
+    admit(job) -> handle           allocate, build operators, matrix functions, upload state
+    plan(handles) -> plan          grouped plan over the handles (in this order)
+    launch(plan, steps) -> token   enqueue `steps` steps of every member
+    fetch(handle, after) -> token  enqueue the download of a state after round `after`
+    wait(token)                    block until the token's work is done
+    result(handle) -> (U, V)       host arrays (after the fetch token completed)
+    release(handle)                free the request's device memory
+    release_plan(plan)             free a plan (no run of it is pending)
+    solve_alone(handle, steps) -> token   (sequential reference path)
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Any, Callable, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Job:
+    """One request.  ``workload`` carries the problem description (grid ``n``,
+    ``domain``, ``diff``, ``vel_u``, ``vel_v``, ``model``, ``params``, ``tau``);
+    ``initial`` returns the host initial state (U0, V0), first index fastest."""
+    rid: int
+    arrival: float                  # seconds after the stream starts
+    workload: Any
+    steps: int
+    initial: Callable[[], tuple]
+
+    @property
+    def N(self) -> int:
+        return int(np.prod(self.workload.n))
+
+
+@dataclasses.dataclass
+class Completion:
+    rid: int
+    arrival: float
+    admitted: float
+    finished: float
+    steps: int
+    grid_points: int
+    status: str = "ok"              # "ok" or "rejected" (larger than the whole budget)
+    result: Optional[tuple] = None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+    @property
+    def wait(self) -> float:
+        return self.admitted - self.arrival
+
+
+@dataclasses.dataclass
+class _Slot:
+    serial: int                     # admission order (identifies the slot in plans)
+    job: Job
+    handle: Any
+    bytes: int
+    admitted: float
+    left: int                       # steps not yet enqueued
+
+
+@dataclasses.dataclass
+class _Round:
+    token: Any
+    plan: int                       # serial of the plan
+    members: List[_Slot]
+    steps: int
+    finishing: List[_Slot]
+    fetches: List[Any]
+
+
+class Engine:
+    """Continuous batching over a backend (see the module docstring)."""
+
+    def __init__(self, backend, budget_bytes: int, max_active: int = 64, max_chunk: int = 32,
+                 depth: int = 2, keep_results: bool = True,
+                 clock: Callable[[], float] = time.perf_counter,
+                 sleep: Callable[[float], None] = time.sleep):
+        if budget_bytes <= 0 or max_active < 1 or max_chunk < 1 or depth < 1:
+            raise ValueError("budget_bytes, max_active, max_chunk and depth must be positive")
+        self.backend = backend
+        self.budget = int(budget_bytes)
+        self.max_active = int(max_active)
+        self.max_chunk = int(max_chunk)
+        self.depth = int(depth)
+        self.keep_results = keep_results
+        self.clock = clock
+        self.sleep = sleep
+        self.stats = {}
+
+    def run(self, jobs: Sequence[Job]) -> List[Completion]:
+        be = self.backend
+        for j in jobs:
+            if j.steps < 0:
+                raise ValueError(f"request {j.rid}: negative step count")
+        pending = collections.deque(sorted(jobs, key=lambda j: (j.arrival, j.rid)))
+        queue: collections.deque = collections.deque()
+        slots: List[_Slot] = []
+        inflight: collections.deque = collections.deque()
+        done: List[Completion] = []
+        used = 0
+        peak_used = peak_active = rounds = nplans = 0
+        serial = 0
+        plans = {}                  # plan serial -> [backend plan, references]
+        plan_id, plan_members = None, ()
+        t0 = self.clock()
+
+        def now():
+            return self.clock() - t0
+
+        def drop_plan(pid):
+            plans[pid][1] -= 1
+            if plans[pid][1] == 0:
+                be.release_plan(plans.pop(pid)[0])
+
+        def finish(s: _Slot, t: float, result=None):
+            nonlocal used
+            done.append(Completion(s.job.rid, s.job.arrival, s.admitted, t, s.job.steps,
+                                   s.job.N, "ok", result))
+            used -= s.bytes
+            slots.remove(s)
+            be.release(s.handle)
+
+        while True:
+            t = now()
+            while pending and pending[0].arrival <= t:
+                queue.append(pending.popleft())
+            # admission: first come, first served, while slots and budget allow
+            while queue and len(slots) < self.max_active:
+                job = queue[0]
+                need = int(be.footprint(job))
+                if need > self.budget:
+                    queue.popleft()
+                    done.append(Completion(job.rid, job.arrival, now(), now(), job.steps, job.N,
+                                           "rejected"))
+                    continue
+                if used + need > self.budget:
+                    break
+                queue.popleft()
+                handle = be.admit(job)
+                used += need
+                serial += 1
+                s = _Slot(serial, job, handle, need, now(), job.steps)
+                slots.append(s)
+                peak_used = max(peak_used, used)
+                peak_active = max(peak_active, len(slots))
+                if job.steps == 0:
+                    res = None
+                    if self.keep_results:
+                        tok = be.fetch(handle, None)
+                        be.wait(tok)
+                        res = be.result(handle)
+                    finish(s, now(), res)
+
+            runnable = [s for s in slots if s.left > 0]
+            if runnable and len(inflight) < self.depth:
+                members = tuple(s.serial for s in runnable)
+                if plan_id is None or members != plan_members:
+                    if plan_id is not None:
+                        drop_plan(plan_id)
+                    serial += 1
+                    nplans += 1
+                    plan_id, plan_members = serial, members
+                    plans[plan_id] = [be.plan([s.handle for s in runnable]), 1]
+                steps = min(self.max_chunk, min(s.left for s in runnable))
+                token = be.launch(plans[plan_id][0], steps)
+                plans[plan_id][1] += 1
+                rounds += 1
+                for s in runnable:
+                    s.left -= steps
+                finishing = [s for s in runnable if s.left == 0]
+                fetches = [be.fetch(s.handle, token) if self.keep_results else token
+                           for s in finishing]
+                inflight.append(_Round(token, plan_id, runnable, steps, finishing, fetches))
+                continue
+            if inflight:
+                r = inflight.popleft()
+                be.wait(r.token)
+                for s, f in zip(r.finishing, r.fetches):
+                    be.wait(f)
+                    finish(s, now(), be.result(s.handle) if self.keep_results else None)
+                drop_plan(r.plan)
+                continue
+            if plan_id is not None:
+                drop_plan(plan_id)
+                plan_id, plan_members = None, ()
+            if pending:
+                self.sleep(max(0.0, pending[0].arrival - now()))
+                continue
+            if queue:   # nothing active, yet the head does not fit: cannot happen
+                raise RuntimeError("admission stalled with an idle device")
+            break
+        end = now()
+        ok = [c for c in done if c.status == "ok"]
+        lat = np.array([c.latency for c in ok]) if ok else np.zeros(1)
+        gps = sum(c.steps * c.grid_points for c in ok)
+        self.stats = {
+            "requests": len(done), "rejected": len(done) - len(ok),
+            "makespan_s": end, "grid_point_steps": gps,
+            "throughput": gps / end if end > 0 else 0.0,
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "mean_wait_s": float(np.mean([c.wait for c in ok])) if ok else 0.0,
+            "peak_bytes": peak_used, "peak_active": peak_active,
+            "rounds": rounds, "plans_built": nplans,
+        }
+        return sorted(done, key=lambda c: c.rid)
+
+
+def run_sequential(backend, jobs: Sequence[Job], keep_results: bool = True,
+                   clock: Callable[[], float] = time.perf_counter,
+                   sleep: Callable[[float], None] = time.sleep):
+    """The plain path for comparison: requests in arrival order, one at a time,
+    each set up and solved alone (adr_solve), no batching or overlap."""
+    t0 = clock()
+    done = []
+    for job in sorted(jobs, key=lambda j: (j.arrival, j.rid)):
+        t = clock() - t0
+        if job.arrival > t:
+            sleep(job.arrival - t)
+        admitted = clock() - t0
+        h = backend.admit(job)
+        tok = backend.solve_alone(h, job.steps)
+        backend.wait(tok)
+        res = None
+        if keep_results:
+            f = backend.fetch(h, tok)
+            backend.wait(f)
+            res = backend.result(h)
+        done.append(Completion(job.rid, job.arrival, admitted, clock() - t0, job.steps, job.N,
+                               "ok", res))
+        backend.release(h)
+    end = clock() - t0
+    lat = np.array([c.latency for c in done]) if done else np.zeros(1)
+    gps = sum(c.steps * c.grid_points for c in done)
+    stats = {"requests": len(done), "makespan_s": end, "grid_point_steps": gps,
+             "throughput": gps / end if end > 0 else 0.0,
+             "p50_latency_s": float(np.percentile(lat, 50)),
+             "p99_latency_s": float(np.percentile(lat, 99))}
+    return done, stats
+
+
+# ----------------------------------------------------------------------------- GPU backend
+
+class _Handle:
+    __slots__ = ("solver", "U", "V", "hostU", "hostV", "shape")
+
+
+class GpuBackend:
+    """Backend on the HIP library: per-request operators and matrix functions
+    built on a set-up stream (adr_build_1d_ops, adr_precompute_phi), grouped
+    plans (adr_batch_*) run on a compute stream, results copied back on a copy
+    stream into pinned host memory.  All streams have the default priority."""
+
+    def __init__(self, precision: str = "f64", device: str = "cuda"):
+        import torch
+        from . import ADR_BATCH_PREPARED, PRECISION_IDS  # noqa: F401
+        if precision not in ("f64", "f32"):
+            raise ValueError("serving runs FP64 or FP32 products")
+        self.torch = torch
+        self.precision = precision
+        self.device = device
+        self.compute = torch.cuda.Stream(device)
+        self.setup = torch.cuda.Stream(device)
+        self.copy = torch.cuda.Stream(device)
+
+    def footprint(self, job: Job) -> int:
+        from . import workspace_bytes_for
+        w = job.workload
+        n = [int(x) for x in w.n]
+        N = int(np.prod(n))
+        ops = sum(2 * (4 * k * k + 3 * k) * 8 for k in n)   # per component: E, phi1, phi2, A, band
+        return 2 * N * 8 + workspace_bytes_for(n, self.precision) + ops
+
+    def admit(self, job: Job):
+        from . import Solver, adr_batch_create, adr_batch_destroy
+        torch = self.torch
+        h = _Handle()
+        with torch.cuda.stream(self.setup):
+            s = Solver(job.workload, precision=self.precision, device=self.device,
+                       stream=self.setup)
+            U0, V0 = job.initial()
+            h.U, h.V = s.upload(U0, V0)
+        if self.precision == "f32":
+            # a plan of one writes the FP32 matrix copies into the workspace once;
+            # the serving plans then skip that (ADR_BATCH_PREPARED)
+            p = adr_batch_create([s.problem], [h.U], [h.V], [s.work], 0, self.setup)
+            adr_batch_destroy(p)
+        self.setup.synchronize()
+        h.solver = s
+        h.shape = s.shape
+        h.hostU = h.hostV = None
+        return h
+
+    def plan(self, handles):
+        from . import ADR_BATCH_PREPARED, adr_batch_create
+        flags = ADR_BATCH_PREPARED if self.precision == "f32" else 0
+        return adr_batch_create([h.solver.problem for h in handles], [h.U for h in handles],
+                                [h.V for h in handles], [h.solver.work for h in handles], flags,
+                                self.setup)
+
+    def launch(self, plan, steps: int):
+        from . import adr_batch_run
+        adr_batch_run(plan, steps, self.compute)
+        ev = self.torch.cuda.Event()
+        ev.record(self.compute)
+        return ev
+
+    def solve_alone(self, h, steps: int):
+        from . import adr_solve
+        adr_solve(h.solver.problem, h.U, h.V, steps, h.solver.work, self.compute)
+        ev = self.torch.cuda.Event()
+        ev.record(self.compute)
+        return ev
+
+    def fetch(self, h, after):
+        torch = self.torch
+        if after is not None:
+            self.copy.wait_event(after)
+        else:
+            self.copy.wait_stream(self.setup)
+        with torch.cuda.stream(self.copy):
+            h.hostU = torch.empty(h.U.numel(), dtype=torch.float64, pin_memory=True)
+            h.hostV = torch.empty(h.V.numel(), dtype=torch.float64, pin_memory=True)
+            h.hostU.copy_(h.U, non_blocking=True)
+            h.hostV.copy_(h.V, non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record(self.copy)
+        return ev
+
+    def wait(self, token):
+        token.synchronize()
+
+    def result(self, h):
+        shape = tuple(h.shape)
+        U = np.asfortranarray(h.hostU.numpy().reshape(shape, order="F").copy())
+        V = np.asfortranarray(h.hostV.numpy().reshape(shape, order="F").copy())
+        return U, V
+
+    def release(self, h):
+        h.solver = h.U = h.V = h.hostU = h.hostV = None
+
+    def release_plan(self, plan):
+        from . import adr_batch_destroy
+        adr_batch_destroy(plan)
