@@ -12,6 +12,12 @@ events on its own stream inside the timed pass), and the CPU oracle timed on
 the host's cores on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--precision f64]
+
+Besides the main line's workload it reports (unless --no-extras): the FP32
+and split-BF16 products on the same grid, the 64-instance batched 2D
+Schnakenberg workload (grouped plans vs one-by-one), and the serving stream's
+p50/p99 latency and throughput (continuous batching vs the plain FP64 path
+one request at a time).
 """
 from __future__ import annotations
 
@@ -90,6 +96,100 @@ def cpu_baseline(workload, steps: int = 2):
     }
 
 
+def _lowp_legs(adr, S, torch, w, steps, seed, ref_state):
+    """Throughput of the reduced-precision products on the same workload, and the
+    difference from the FP64 GPU path after the same steps."""
+    out = {}
+    import numpy as np
+    for prec in ("f32", "bf16x3"):
+        solver = adr.Solver(w, precision=prec)
+        U0, V0 = S.initial_state(w, seed)
+        Ud, Vd = solver.upload(U0, V0)
+        solver.solve(Ud, Vd, 2)                       # warm
+        Ud2, Vd2 = solver.upload(U0, V0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solver.solve(Ud2, Vd2, steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        err = None
+        if ref_state is not None:
+            Ur, Vr = ref_state
+            err = max(float((Ud2 - Ur).abs().max() / Ur.abs().max()),
+                      float((Vd2 - Vr).abs().max() / Vr.abs().max()))
+        out[prec] = {"value": w.N * steps / dt, "ms_per_step": 1e3 * dt / steps, "steps": steps,
+                     "rel_inf_err_vs_f64_gpu": err}
+        del solver, Ud, Vd, Ud2, Vd2
+    return out
+
+
+def _batched_leg(adr, S, torch, steps, seed):
+    """The 64-instance batched 2D Schnakenberg workload: grouped plans (FP64 with
+    autotuned tiles, FP32), each captured in a graph, against the same instances
+    stepped one by one with adr_solve."""
+    works = S.batched_schnakenberg_2d(64, steps, seed=seed)
+    total = sum(w.N for w in works)
+    out = {"workload": "64 x 2D Schnakenberg, sides drawn from {64..512}, tau=1e-3",
+           "grid_points": total, "steps": steps}
+    init = [S.initial_state(w, seed + 1 + k) for k, w in enumerate(works)]
+    for prec in ("f64", "f32"):
+        solvers = [adr.Solver(w, precision=prec) for w in works]
+        states = [s.upload(*u) for s, u in zip(solvers, init)]
+        flags = adr.ADR_BATCH_GRAPH | (adr.ADR_BATCH_AUTOTUNE if prec == "f64" else 0)
+        b = adr.Batch(solvers, states, flags)
+        b.run(3)                                       # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        cfg, graph = b.info()
+        b.close()
+        out[prec] = {"value": total * steps / dt, "ms_per_step": 1e3 * dt / steps,
+                     "tile_cfg_per_mu": cfg[:2], "graph": graph}
+        if prec == "f64":
+            t0 = time.perf_counter()
+            for s, (Ud, Vd) in zip(solvers, states):
+                s.solve(Ud, Vd, steps)
+            torch.cuda.synchronize()
+            dt1 = time.perf_counter() - t0
+            out["f64_one_by_one"] = {"value": total * steps / dt1, "ms_per_step": 1e3 * dt1 / steps}
+        del solvers, states
+    return out
+
+
+def _serving_leg(S, count, rate, budget_gib, seed):
+    """The serving stream: Poisson arrivals of mixed 2D/3D requests, served by the
+    continuous-batching engine and, for comparison, one at a time by the plain
+    FP64 path, on the same arrival times."""
+    from paper_2307_10684_amd import serving
+    reqs = S.serving_stream(count, rate, seed)
+    payload = {r.rid: S.initial_state(r.workload, r.seed) for r in reqs}
+    jobs = [serving.Job(r.rid, r.arrival, r.workload, r.workload.steps,
+                        lambda k=r.rid: payload[k]) for r in reqs]
+    be = serving.GpuBackend("f64")
+    # warm the set-up path once (first use of the matrix-function kernels)
+    serving.Engine(be, budget_bytes=budget_gib << 30).run(
+        [serving.Job(-1, 0.0, jobs[0].workload, 2, jobs[0].initial)])
+    eng = serving.Engine(be, budget_bytes=budget_gib << 30, max_active=64, max_chunk=16,
+                         lane_bounds=(4e9,), keep_results=True)
+    eng.run(jobs)
+    _, seq = serving.run_sequential(be, jobs, keep_results=True)
+    keys = ("p50_latency_s", "p99_latency_s", "throughput", "makespan_s", "mean_wait_s",
+            "peak_active", "peak_bytes", "rounds", "plans_built", "lanes")
+    return {
+        "workload": f"{count} requests, Poisson rate {rate}/s: 50% 2D Schnakenberg 128^2-1024^2, "
+                    "25% 3D FHN, 25% 3D advective Brusselator 32^3-192^3, 50-500 steps, "
+                    "tau in [1e-4, 5e-3]",
+        "budget_gib": budget_gib,
+        "grid_point_steps": eng.stats["grid_point_steps"],
+        "continuous_batching_f64": {k: eng.stats[k] for k in keys},
+        "sequential_plain_f64": {k: seq[k] for k in ("p50_latency_s", "p99_latency_s",
+                                                     "throughput", "makespan_s")},
+        "throughput_unit": "grid-point-steps/s",
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +201,13 @@ def main(argv=None):
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the main workload (no reduced-precision, batched or serving legs)")
+    ap.add_argument("--lowp-steps", type=int, default=20)
+    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-budget-gib", type=int, default=16)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of this many MiB three times "
                          "(reference traffic for hardware byte counters)")
@@ -162,6 +269,27 @@ def main(argv=None):
     n_stage, ms_stage = adr.adr_timing_read(1)
     adr.adr_timing_enable(0)
 
+    if not args.no_extras:
+        # FP64 state after `lowp_steps` steps, the reference of the reduced precisions
+        ref = None
+        if args.precision == "f64" and args.scheme == "etd2rkds":
+            Ud.copy_(U_init)
+            Vd.copy_(V_init)
+            solver.solve(Ud, Vd, args.lowp_steps)
+            torch.cuda.synchronize()
+            ref = (Ud.clone(), Vd.clone())
+        del U_init, V_init, Ud, Vd, solver
+        torch.cuda.empty_cache()
+        extras = {"precisions": _lowp_legs(adr, S, torch, w, args.lowp_steps, args.seed, ref)}
+        del ref
+        torch.cuda.empty_cache()
+        extras["batched"] = _batched_leg(adr, S, torch, args.batch_steps, args.seed)
+        torch.cuda.empty_cache()
+        extras["serving"] = _serving_leg(S, args.serve_requests, args.serve_rate,
+                                         args.serve_budget_gib, args.seed)
+    else:
+        extras = {}
+
     ms_per_step = 1e3 * elapsed / args.steps
     value = N * args.steps / elapsed
     mode_avg_ms = ms_mode / max(n_mode, 1)
@@ -222,6 +350,11 @@ def main(argv=None):
         "paper_context": "paper (MATLAB, i7-10750H 6 cores): 64^3 Brusselator ETD2RKds 9.1e-3 s/step "
                          "= 2.9e7 grid-point-steps/s",
     }
+    if extras:
+        if args.precision == "f64":
+            extras["precisions"]["f64"] = {"value": value, "ms_per_step": ms_per_step,
+                                           "steps": args.steps}
+        line.update(extras)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(line), flush=True)

@@ -11,7 +11,9 @@ never takes a request past its step count, and a finished request's state is
 copied back while the next round already runs.  Rounds are pipelined
 ``depth`` deep: while the device works on round k, the host admits new
 arrivals (building their operators and matrix functions on a side stream) and
-queues round k+1 with a plan that includes them.
+queues round k+1 with a plan that includes them.  Requests of very different
+size run in separate lanes (plans on separate streams) so that a small
+request is not held to the step rate of a large one.
 
 The engine is pure scheduling logic.  The device work goes through a backend
 object; ``GpuBackend`` below drives the HIP library, and the tests drive the
@@ -22,8 +24,10 @@ Backend protocol::
     footprint(job) -> int          device bytes the request holds while admitted
     admit(job) -> handle           allocate, build operators, matrix functions, upload state
     plan(handles) -> plan          grouped plan over the handles (in this order)
-    launch(plan, steps) -> token   enqueue `steps` steps of every member
+    launch(plan, steps, lane) -> token   enqueue `steps` steps of every member on the
+                                   lane's stream
     fetch(handle, after) -> token  enqueue the download of a state after round `after`
+    ready(token) -> bool           whether the token's work is done (no blocking)
     wait(token)                    block until the token's work is done
     result(handle) -> (U, V)       host arrays (after the fetch token completed)
     release(handle)                free the request's device memory
@@ -96,24 +100,61 @@ class _Round:
     fetches: List[Any]
 
 
+class _Lane:
+    """Requests of one size class: their own plan, rounds and stream."""
+
+    def __init__(self, index: int):
+        self.index = index
+        self.inflight: collections.deque = collections.deque()
+        self.plan_id = None
+        self.members = ()
+
+
+def step_flops(workload) -> float:
+    """Multiply-adds x 2 of one ETD2RKds step's four Tucker operators on the
+    grid: 8 * N * sum(n_mu) (Sec. 3, eq. (11); Sec. 2 for the mode products)."""
+    n = [int(x) for x in workload.n]
+    return 8.0 * float(np.prod(n)) * float(sum(n))
+
+
 class Engine:
-    """Continuous batching over a backend (see the module docstring)."""
+    """Continuous batching over a backend (see the module docstring).
+
+    Admitted requests are split into lanes by the work of one step
+    (``lane_bounds``, ascending thresholds in flops; the default puts steps of
+    4 GFLOP and more, about what fills the device for one step, in their own
+    lane): each lane has its own
+    plan, its own rounds and its own device stream, so small requests keep
+    their own step rate beside large ones and their kernels fill the compute
+    units that the large ones leave idle.  The loop polls the rounds in flight
+    (``backend.ready``), so arrivals are admitted as soon as they come.
+    """
 
     def __init__(self, backend, budget_bytes: int, max_active: int = 64, max_chunk: int = 32,
                  depth: int = 2, keep_results: bool = True,
+                 lane_bounds: Sequence[float] = (4e9,),
+                 poll_s: float = 2e-4,
                  clock: Callable[[], float] = time.perf_counter,
                  sleep: Callable[[float], None] = time.sleep):
-        if budget_bytes <= 0 or max_active < 1 or max_chunk < 1 or depth < 1:
-            raise ValueError("budget_bytes, max_active, max_chunk and depth must be positive")
+        if budget_bytes <= 0 or max_active < 1 or max_chunk < 1 or depth < 1 or poll_s <= 0:
+            raise ValueError("budget_bytes, max_active, max_chunk, depth and poll_s must be positive")
+        if list(lane_bounds) != sorted(lane_bounds):
+            raise ValueError("lane_bounds must be ascending")
         self.backend = backend
         self.budget = int(budget_bytes)
         self.max_active = int(max_active)
         self.max_chunk = int(max_chunk)
         self.depth = int(depth)
         self.keep_results = keep_results
+        self.lane_bounds = [float(b) for b in lane_bounds]
+        self.poll_s = float(poll_s)
         self.clock = clock
         self.sleep = sleep
         self.stats = {}
+
+    def lane_of(self, job: Job) -> int:
+        f = step_flops(job.workload)
+        return sum(1 for b in self.lane_bounds if f >= b)
 
     def run(self, jobs: Sequence[Job]) -> List[Completion]:
         be = self.backend
@@ -123,13 +164,13 @@ class Engine:
         pending = collections.deque(sorted(jobs, key=lambda j: (j.arrival, j.rid)))
         queue: collections.deque = collections.deque()
         slots: List[_Slot] = []
-        inflight: collections.deque = collections.deque()
+        lanes = [_Lane(k) for k in range(len(self.lane_bounds) + 1)]
+        lane_of_slot = {}
         done: List[Completion] = []
         used = 0
         peak_used = peak_active = rounds = nplans = 0
         serial = 0
         plans = {}                  # plan serial -> [backend plan, references]
-        plan_id, plan_members = None, ()
         t0 = self.clock()
 
         def now():
@@ -146,6 +187,7 @@ class Engine:
                                    s.job.N, "ok", result))
             used -= s.bytes
             slots.remove(s)
+            lane_of_slot.pop(s.serial, None)
             be.release(s.handle)
 
         while True:
@@ -169,6 +211,7 @@ class Engine:
                 serial += 1
                 s = _Slot(serial, job, handle, need, now(), job.steps)
                 slots.append(s)
+                lane_of_slot[s.serial] = self.lane_of(job)
                 peak_used = max(peak_used, used)
                 peak_active = max(peak_active, len(slots))
                 if job.steps == 0:
@@ -179,44 +222,59 @@ class Engine:
                         res = be.result(handle)
                     finish(s, now(), res)
 
-            runnable = [s for s in slots if s.left > 0]
-            if runnable and len(inflight) < self.depth:
+            progressed = False
+            # completed rounds (oldest first in each lane)
+            for ln in lanes:
+                while ln.inflight:
+                    r = ln.inflight[0]
+                    if not (be.ready(r.token) and all(be.ready(f) for f in r.fetches)):
+                        break
+                    ln.inflight.popleft()
+                    for s in r.finishing:
+                        finish(s, now(), be.result(s.handle) if self.keep_results else None)
+                    drop_plan(r.plan)
+                    progressed = True
+            # new rounds
+            for ln in lanes:
+                runnable = [s for s in slots if s.left > 0 and lane_of_slot[s.serial] == ln.index]
+                if not runnable:
+                    if ln.plan_id is not None:
+                        drop_plan(ln.plan_id)
+                        ln.plan_id, ln.members = None, ()
+                    continue
+                if len(ln.inflight) >= self.depth:
+                    continue
                 members = tuple(s.serial for s in runnable)
-                if plan_id is None or members != plan_members:
-                    if plan_id is not None:
-                        drop_plan(plan_id)
+                if ln.plan_id is None or members != ln.members:
+                    if ln.plan_id is not None:
+                        drop_plan(ln.plan_id)
                     serial += 1
                     nplans += 1
-                    plan_id, plan_members = serial, members
-                    plans[plan_id] = [be.plan([s.handle for s in runnable]), 1]
+                    ln.plan_id, ln.members = serial, members
+                    plans[ln.plan_id] = [be.plan([s.handle for s in runnable]), 1]
                 steps = min(self.max_chunk, min(s.left for s in runnable))
-                token = be.launch(plans[plan_id][0], steps)
-                plans[plan_id][1] += 1
+                token = be.launch(plans[ln.plan_id][0], steps, ln.index)
+                plans[ln.plan_id][1] += 1
                 rounds += 1
                 for s in runnable:
                     s.left -= steps
                 finishing = [s for s in runnable if s.left == 0]
                 fetches = [be.fetch(s.handle, token) if self.keep_results else token
                            for s in finishing]
-                inflight.append(_Round(token, plan_id, runnable, steps, finishing, fetches))
+                ln.inflight.append(_Round(token, ln.plan_id, runnable, steps, finishing, fetches))
+                progressed = True
+            if progressed:
                 continue
-            if inflight:
-                r = inflight.popleft()
-                be.wait(r.token)
-                for s, f in zip(r.finishing, r.fetches):
-                    be.wait(f)
-                    finish(s, now(), be.result(s.handle) if self.keep_results else None)
-                drop_plan(r.plan)
+            if any(ln.inflight for ln in lanes):
+                self.sleep(self.poll_s)
                 continue
-            if plan_id is not None:
-                drop_plan(plan_id)
-                plan_id, plan_members = None, ()
             if pending:
                 self.sleep(max(0.0, pending[0].arrival - now()))
                 continue
             if queue:   # nothing active, yet the head does not fit: cannot happen
                 raise RuntimeError("admission stalled with an idle device")
             break
+        assert not plans, "plans left behind"
         end = now()
         ok = [c for c in done if c.status == "ok"]
         lat = np.array([c.latency for c in ok]) if ok else np.zeros(1)
@@ -229,7 +287,7 @@ class Engine:
             "p99_latency_s": float(np.percentile(lat, 99)),
             "mean_wait_s": float(np.mean([c.wait for c in ok])) if ok else 0.0,
             "peak_bytes": peak_used, "peak_active": peak_active,
-            "rounds": rounds, "plans_built": nplans,
+            "rounds": rounds, "plans_built": nplans, "lanes": len(lanes),
         }
         return sorted(done, key=lambda c: c.rid)
 
@@ -276,8 +334,9 @@ class _Handle:
 class GpuBackend:
     """Backend on the HIP library: per-request operators and matrix functions
     built on a set-up stream (adr_build_1d_ops, adr_precompute_phi), grouped
-    plans (adr_batch_*) run on a compute stream, results copied back on a copy
-    stream into pinned host memory.  All streams have the default priority."""
+    plans (adr_batch_*) run on one compute stream per lane, results copied back
+    on a copy stream into pinned host memory.  All streams have the default
+    priority."""
 
     def __init__(self, precision: str = "f64", device: str = "cuda"):
         import torch
@@ -287,9 +346,14 @@ class GpuBackend:
         self.torch = torch
         self.precision = precision
         self.device = device
-        self.compute = torch.cuda.Stream(device)
+        self.lanes = {}             # lane -> compute stream (created on first use)
         self.setup = torch.cuda.Stream(device)
         self.copy = torch.cuda.Stream(device)
+
+    def _lane(self, lane: int):
+        if lane not in self.lanes:
+            self.lanes[lane] = self.torch.cuda.Stream(self.device)
+        return self.lanes[lane]
 
     def footprint(self, job: Job) -> int:
         from . import workspace_bytes_for
@@ -326,18 +390,20 @@ class GpuBackend:
                                 [h.V for h in handles], [h.solver.work for h in handles], flags,
                                 self.setup)
 
-    def launch(self, plan, steps: int):
+    def launch(self, plan, steps: int, lane: int = 0):
         from . import adr_batch_run
-        adr_batch_run(plan, steps, self.compute)
+        st = self._lane(lane)
+        adr_batch_run(plan, steps, st)
         ev = self.torch.cuda.Event()
-        ev.record(self.compute)
+        ev.record(st)
         return ev
 
     def solve_alone(self, h, steps: int):
         from . import adr_solve
-        adr_solve(h.solver.problem, h.U, h.V, steps, h.solver.work, self.compute)
+        st = self._lane(0)
+        adr_solve(h.solver.problem, h.U, h.V, steps, h.solver.work, st)
         ev = self.torch.cuda.Event()
-        ev.record(self.compute)
+        ev.record(st)
         return ev
 
     def fetch(self, h, after):
@@ -354,6 +420,9 @@ class GpuBackend:
         ev = torch.cuda.Event()
         ev.record(self.copy)
         return ev
+
+    def ready(self, token) -> bool:
+        return token.query()
 
     def wait(self, token):
         token.synchronize()

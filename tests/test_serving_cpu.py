@@ -40,7 +40,7 @@ class FakeBackend:
 
     def __init__(self, clock, cost=1e-6, setup=1e-4):
         self.clock, self.cost, self.setup = clock, cost, setup
-        self.device_free = 0.0
+        self.device_free = {}      # lane -> time its stream is free
         self.mem = 0
         self.peak_mem = 0
         self.live = 0
@@ -70,23 +70,23 @@ class FakeBackend:
         self.plans_alive += 1
         return list(handles)
 
-    def _round(self, plan, steps):
+    def _round(self, plan, steps, lane=0):
         for h in plan:
             assert not h["released"], "a released request was launched"
             for _ in range(steps):
                 h["U"], h["V"] = O.etd2rkds_step(h["U"], h["V"], h["p"], h["mats"])
             h["steps"] += steps
-        start = max(self.device_free, self.clock.t)
-        self.device_free = start + self.cost * steps * sum(h["job"].N for h in plan)
+        start = max(self.device_free.get(lane, 0.0), self.clock.t)
+        self.device_free[lane] = start + self.cost * steps * sum(h["job"].N for h in plan)
         self._tok += 1
-        tok = ("round", self._tok, self.device_free)
+        tok = ("round", self._tok, self.device_free[lane])
         self.outstanding.add(tok[1])
         self.peak_outstanding = max(self.peak_outstanding, len(self.outstanding))
-        self.rounds.append(([h["job"].rid for h in plan], steps))
+        self.rounds.append(([h["job"].rid for h in plan], steps, lane))
         return tok
 
-    def launch(self, plan, steps):
-        return self._round(plan, steps)
+    def launch(self, plan, steps, lane=0):
+        return self._round(plan, steps, lane)
 
     def solve_alone(self, h, steps):
         return self._round([h], steps)
@@ -94,6 +94,12 @@ class FakeBackend:
     def fetch(self, h, after):
         h["out"] = (h["U"].copy(), h["V"].copy())
         return ("fetch", None, after[2] if after else self.clock.t)
+
+    def ready(self, token):
+        done = self.clock.t >= token[2]
+        if done and token[0] == "round":
+            self.outstanding.discard(token[1])
+        return done
 
     def wait(self, token):
         if token[0] == "round":
@@ -166,7 +172,7 @@ def test_requests_join_while_others_run():
     jobs = _jobs(8, seed=1, spacing=0.001)
     done = _engine(clock, be, max_chunk=2).run(jobs)
     # some round holds several requests, and some request joined a running mix
-    assert max(len(m) for m, _ in be.rounds) >= 3
+    assert max(len(r[0]) for r in be.rounds) >= 3
     joined = any(a.admitted > b.admitted and a.admitted < b.finished
                  for a in done for b in done if a.rid != b.rid)
     assert joined
@@ -198,6 +204,26 @@ def test_slot_limit_and_pipeline_depth():
     eng.run(_jobs(9, seed=3, spacing=1e-5))
     assert be.peak_live <= 3 and eng.stats["peak_active"] <= 3
     assert be.peak_outstanding <= 2
+
+
+def test_lanes_separate_small_and_large_requests():
+    clock = Clock()
+    be = FakeBackend(clock)
+    jobs = _jobs(10, seed=7, spacing=1e-4)
+    flops = sorted(serving.step_flops(j.workload) for j in jobs)
+    bound = flops[len(flops) // 2]
+    eng = _engine(clock, be, lane_bounds=[bound], max_chunk=3)
+    done = eng.run(jobs)
+    lane = {j.rid: int(serving.step_flops(j.workload) >= bound) for j in jobs}
+    for members, _, ln in be.rounds:
+        assert all(lane[r] == ln for r in members)
+    assert {ln for _, _, ln in be.rounds} == {0, 1}
+    for c, j in zip(done, jobs):
+        U, V = _alone(j)
+        assert np.array_equal(c.result[0], U) and np.array_equal(c.result[1], V)
+    assert be.plans_alive == 0 and be.live == 0
+    with pytest.raises(ValueError):
+        _engine(clock, be, lane_bounds=[2.0, 1.0])
 
 
 def test_request_larger_than_the_budget_is_rejected_not_stalled():
