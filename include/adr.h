@@ -57,8 +57,13 @@ enum adr_precision { ADR_F64 = 0,                   /* all arithmetic in FP64 */
  *   ADR_SCHNAKENBERG (gamma, a, b):   gamma(a - u + u^2 v),  gamma(b - u^2 v)    Sec. 4.1 eq. (12)
  *   ADR_FHN          (rho, eps, a1, a0): rho(u - u^3 - v),  rho eps(u - a1 v - a0)  Secs. 4.2-4.3
  *   ADR_BRUSSELATOR  (A, B):          A - (B+1)u + u^2 v,    B u - u^2 v        Sec. 4.6 eq. (17)
- *   ADR_ZERO         ():              0, 0  (pure advection-diffusion)            */
-enum adr_model { ADR_SCHNAKENBERG = 0, ADR_FHN = 1, ADR_BRUSSELATOR = 2, ADR_ZERO = 3 };
+ *   ADR_ZERO         ():              0, 0  (pure advection-diffusion)
+ *   ADR_DIB          (rho, a1u, a2u, a3u, a4u, a1v, a2v, a3v, a4v, a5v):        Sec. 4.4 eq. (15)
+ *                    rho(a1u(1-v)u - a2u u^3 - a3u(v - a4u)),
+ *                    rho(a1v(1+a2v u)(1-v)(1-a3v(1-v)) - a4v v(1+a5v u)(1+a3v v)) */
+enum adr_model { ADR_SCHNAKENBERG = 0, ADR_FHN = 1, ADR_BRUSSELATOR = 2, ADR_ZERO = 3,
+                 ADR_DIB = 4 };
+#define ADR_MAX_PARAMS 12
 
 #define ADR_MAX_DIM 3
 
@@ -113,7 +118,7 @@ typedef struct adr_problem {
   int32_t scheme;              /* enum adr_scheme */
   int32_t precision;           /* enum adr_precision */
   int32_t flags;               /* reserved, must be 0 */
-  double params[8];            /* model constants, order as in enum adr_model */
+  double params[ADR_MAX_PARAMS]; /* model constants, order as in enum adr_model; rest unused */
   double tau;                  /* time step, > 0 (used for the stage scalings) */
   /* phi[c][j][mu]: device n[mu] x n[mu] FP64 column-major matrices of
    * component c (0 = u, 1 = v), j = 0: e^{tau A}, 1: phi_1(tau A), 2: phi_2(tau A).
@@ -176,6 +181,42 @@ int adr_tucker(int d, const int32_t* n, const double* const* M, const double* W,
  * copy used to calibrate hardware byte counters against known traffic.
  */
 int adr_device_copy(const double* in, double* out, size_t count, void* stream);
+
+/*
+ * Dynamics indicators (Sec. 4, opening paragraphs): the spatial mean <C> of
+ * each component, an approximation of (1/|Omega|) times the integral of the
+ * field, here by the trapezoidal rule on the node-centred grid (weights 1/2 on
+ * boundary nodes in each direction, normalised by prod_mu (n_mu - 1)); the
+ * Frobenius norm of the time increment ||C_{n+1} - C_n||_F; and the number of
+ * grid points where any input holds NaN or +-inf.  One fused, deterministic
+ * reduction (no atomics).
+ *
+ * adr_indicators -- rec (device, 5 doubles) = { <U>, <V>, ||U - Uprev||_F,
+ *   ||V - Vprev||_F, non-finite count }.  Uprev and Vprev are both device
+ *   tensors or both NULL (then rec[2] = rec[3] = 0).  work: device scratch of
+ *   adr_indicators_workspace_bytes(d, n) bytes.  Errors: ADR_EINVAL,
+ *   ADR_ENOMEM, ADR_EDEVICE.
+ */
+size_t adr_indicators_workspace_bytes(int d, const int32_t* n);
+int adr_indicators(int d, const int32_t* n, const double* U, const double* V,
+                   const double* Uprev, const double* Vprev, double* rec, void* work,
+                   size_t work_bytes, void* stream);
+
+/*
+ * adr_solve_monitored -- adr_solve, plus the indicators of every `every`-th
+ * step (the increment of that step): record k = 0 .. nsteps/every - 1 at
+ * rec + 5k (device), taken after step (k+1)*every.
+ *   mwork   device, 256-byte aligned, adr_monitor_workspace_bytes(p) bytes
+ *           (a copy of the state before each recorded step, and the
+ *           reduction scratch)
+ * Synchronises `stream` once at the end (only if a record was taken) and
+ * returns ADR_ENONFINITE if any record counted a non-finite value (the steps
+ * and records are still all done).  Other errors as adr_solve.
+ */
+size_t adr_monitor_workspace_bytes(const adr_problem* p);
+int adr_solve_monitored(const adr_problem* p, double* U, double* V, int nsteps, int every,
+                        double* rec, void* work, size_t work_bytes, void* mwork,
+                        size_t mwork_bytes, void* stream);
 
 /*
  * Grouped multi-problem ETD2RKds ("batch plans").  Sec. 3 eq. (11) is applied

@@ -27,6 +27,8 @@ from .models import reaction
 from .integrators import (Problem, problem_from_workload, precompute, etd2rkds_step,
                           lawson2b_step, etd2rk_dense_step, solve, split_phi_dense)
 from .metrics import relative_error, observed_order, rel_inf_error
+from .indicators import (trapezoid_weights, spatial_mean, increment_norm, nonfinite_count,
+                         indicators)
 
 __all__ = [
     "grid_nodes", "laplacian_1d", "advection_1d", "operator_1d", "kron_sum_dense",
@@ -36,4 +38,5 @@ __all__ = [
     "Problem", "problem_from_workload", "precompute", "etd2rkds_step",
     "lawson2b_step", "etd2rk_dense_step", "solve", "split_phi_dense",
     "relative_error", "observed_order", "rel_inf_error",
+    "trapezoid_weights", "spatial_mean", "increment_norm", "nonfinite_count", "indicators",
 ]

@@ -26,11 +26,12 @@ ADR_OK, ADR_EINVAL, ADR_ENOMEM, ADR_EDEVICE, ADR_ENOTSUP, ADR_ENONFINITE = 0, -1
 ADR_BC_NEUMANN = 0
 ADR_ETD2RKDS, ADR_LAWSON2B = 0, 1
 ADR_F64, ADR_F32, ADR_BF16X3 = 0, 1, 2
-ADR_SCHNAKENBERG, ADR_FHN, ADR_BRUSSELATOR, ADR_ZERO = 0, 1, 2, 3
+ADR_SCHNAKENBERG, ADR_FHN, ADR_BRUSSELATOR, ADR_ZERO, ADR_DIB = 0, 1, 2, 3, 4
+ADR_MAX_PARAMS = 12
 ADR_BATCH_AUTOTUNE, ADR_BATCH_GRAPH, ADR_BATCH_PREPARED = 1, 2, 4
 
 MODEL_IDS = {"schnakenberg": ADR_SCHNAKENBERG, "fhn": ADR_FHN,
-             "brusselator": ADR_BRUSSELATOR, "zero": ADR_ZERO}
+             "brusselator": ADR_BRUSSELATOR, "zero": ADR_ZERO, "dib": ADR_DIB}
 SCHEME_IDS = {"etd2rkds": ADR_ETD2RKDS, "lawson2b": ADR_LAWSON2B}
 PRECISION_IDS = {"f64": ADR_F64, "f32": ADR_F32, "bf16x3": ADR_BF16X3}
 
@@ -47,7 +48,7 @@ class AdrProblem(ctypes.Structure):
         ("scheme", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("flags", ctypes.c_int32),
-        ("params", ctypes.c_double * 8),
+        ("params", ctypes.c_double * 12),
         ("tau", ctypes.c_double),
         ("phi", ((ctypes.c_void_p * 3) * 3) * 2),
         ("band", (ctypes.c_void_p * 3) * 2),
@@ -64,7 +65,7 @@ class AdrError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
-            f"{LIB_PATH} is missing: build it with `python -m paper_2307_10684_amd.build` "
+            f"{LIB_PATH} is missing: build it with `python paper_2307_10684_amd/build.py` "
             "(there is no CPU fallback)")
     lib = ctypes.CDLL(LIB_PATH)
     c_int, c_double, c_size, c_void = ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_void_p
@@ -84,6 +85,12 @@ def _load():
         "adr_device_copy": (c_int, [c_void, c_void, c_size, c_void]),
         "adr_timing_enable": (c_int, [c_int]),
         "adr_timing_read": (c_int, [c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_double)]),
+        "adr_indicators_workspace_bytes": (c_size, [c_int, ctypes.POINTER(ctypes.c_int32)]),
+        "adr_indicators": (c_int, [c_int, ctypes.POINTER(ctypes.c_int32), c_void, c_void, c_void, c_void,
+                                   c_void, c_void, c_size, c_void]),
+        "adr_monitor_workspace_bytes": (c_size, [ctypes.POINTER(AdrProblem)]),
+        "adr_solve_monitored": (c_int, [ctypes.POINTER(AdrProblem), c_void, c_void, c_int, c_int, c_void,
+                                        c_void, c_size, c_void, c_size, c_void]),
         "adr_batch_create": (c_int, [c_int, ctypes.POINTER(AdrProblem), ctypes.POINTER(c_void),
                                      ctypes.POINTER(c_void), ctypes.POINTER(c_void),
                                      ctypes.POINTER(c_size), c_int, c_void, ctypes.POINTER(c_void)]),
@@ -102,8 +109,9 @@ _lib = _load()
 EXPORTED = ("adr_strerror", "adr_version", "adr_build_1d_ops", "adr_precompute_phi",
             "adr_workspace_bytes", "adr_step", "adr_solve", "adr_mode_product",
             "adr_tucker_workspace_bytes", "adr_tucker", "adr_device_copy",
-            "adr_timing_enable", "adr_timing_read", "adr_batch_create", "adr_batch_run",
-            "adr_batch_info", "adr_batch_destroy")
+            "adr_timing_enable", "adr_timing_read", "adr_indicators_workspace_bytes",
+            "adr_indicators", "adr_monitor_workspace_bytes", "adr_solve_monitored",
+            "adr_batch_create", "adr_batch_run", "adr_batch_info", "adr_batch_destroy")
 
 
 def _check(status: int, where: str):
@@ -217,6 +225,43 @@ def adr_timing_read(kind: int):
     _check(_lib.adr_timing_read(int(kind), ctypes.byref(launches), ctypes.byref(total)),
            "adr_timing_read")
     return launches.value, total.value
+
+
+def adr_indicators_workspace_bytes(n: Sequence[int]) -> int:
+    return int(_lib.adr_indicators_workspace_bytes(len(n), _dims(n)))
+
+
+def adr_indicators(n: Sequence[int], U, V, Uprev=None, Vprev=None, rec=None, work=None,
+                   stream=None):
+    """The five indicators of (U, V) (and the increment from (Uprev, Vprev)) into the
+    device tensor ``rec`` (5 doubles, allocated if not given); returns ``rec``."""
+    dev = U.device
+    if rec is None:
+        rec = torch.empty(5, dtype=torch.float64, device=dev)
+    if work is None:
+        work = torch.empty((adr_indicators_workspace_bytes(n) + 7) // 8, dtype=torch.float64,
+                           device=dev)
+    _check(_lib.adr_indicators(len(n), _dims(n), _ptr(U), _ptr(V), _ptr(Uprev), _ptr(Vprev),
+                               _ptr(rec), _ptr(work), work.numel() * work.element_size(),
+                               _stream(stream)), "adr_indicators")
+    return rec
+
+
+def adr_monitor_workspace_bytes(problem: AdrProblem) -> int:
+    return int(_lib.adr_monitor_workspace_bytes(ctypes.byref(problem)))
+
+
+def adr_solve_monitored(problem: AdrProblem, U, V, nsteps: int, every: int, rec, work, mwork,
+                        stream=None) -> int:
+    """Returns ADR_OK or ADR_ENONFINITE (a record counted non-finite values);
+    raises on other errors."""
+    st = _lib.adr_solve_monitored(ctypes.byref(problem), _ptr(U), _ptr(V), int(nsteps),
+                                  int(every), _ptr(rec), _ptr(work),
+                                  work.numel() * work.element_size(), _ptr(mwork),
+                                  mwork.numel() * mwork.element_size(), _stream(stream))
+    if st not in (ADR_OK, ADR_ENONFINITE):
+        raise AdrError(st, "adr_solve_monitored")
+    return st
 
 
 def adr_batch_create(problems: Sequence[AdrProblem], U, V, works, flags: int = 0, stream=None) -> int:
@@ -364,6 +409,20 @@ class Solver:
 
     def solve(self, U_dev, V_dev, nsteps: int):
         adr_solve(self.problem, U_dev, V_dev, nsteps, self.work, self.stream)
+
+    def solve_monitored(self, U_dev, V_dev, nsteps: int, every: int = 1):
+        """Solve and record the indicators every `every` steps.  Returns
+        (records as a (nsteps // every, 5) numpy array: <U>, <V>, ||dU||_F,
+        ||dV||_F, non-finite count; status ADR_OK or ADR_ENONFINITE)."""
+        k = max(nsteps // every, 1)
+        rec = torch.zeros(5 * k, dtype=torch.float64, device=self.device)
+        if getattr(self, "mwork", None) is None:
+            nb = adr_monitor_workspace_bytes(self.problem)
+            self.mwork = torch.empty((nb + 7) // 8, dtype=torch.float64, device=self.device)
+        st = adr_solve_monitored(self.problem, U_dev, V_dev, nsteps, every, rec, self.work,
+                                 self.mwork, self.stream)
+        torch.cuda.synchronize()
+        return rec.cpu().numpy().reshape(k, 5)[: nsteps // every], st
 
 
 class Batch:

@@ -1,6 +1,8 @@
 """Build libadr.so (the HIP kernels and the C ABI of include/adr.h) for gfx950.
 
-Run ``python -m paper_2307_10684_amd.build`` (or ``__graft_entry__.build()``).
+Run ``python paper_2307_10684_amd/build.py`` (or ``__graft_entry__.build()``).
+This file imports nothing from the package, whose import needs the built
+library, so it also works on a fresh checkout or with a stale library.
 Every call recompiles all sources with hipcc; objects go to ``_build/`` and
 the shared library is written next to this file, where the binding loads it.
 """

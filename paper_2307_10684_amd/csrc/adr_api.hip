@@ -104,12 +104,12 @@ static bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 int check_problem(const adr_problem* p, Geometry& g) {
   if (!p) return ADR_EINVAL;
   if (p->d < 1 || p->d > ADR_MAX_DIM) return ADR_EINVAL;
-  if (p->model < ADR_SCHNAKENBERG || p->model > ADR_ZERO) return ADR_EINVAL;
+  if (p->model < ADR_SCHNAKENBERG || p->model > ADR_DIB) return ADR_EINVAL;
   if (p->scheme != ADR_ETD2RKDS && p->scheme != ADR_LAWSON2B) return ADR_EINVAL;
   if (p->precision < ADR_F64 || p->precision > ADR_BF16X3) return ADR_EINVAL;
   if (p->flags != 0) return ADR_EINVAL;
   if (!finite_pos(p->tau)) return ADR_EINVAL;
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < ADR_MAX_PARAMS; ++i)
     if (!std::isfinite(p->params[i])) return ADR_EINVAL;
   g.d = p->d;
   g.N = 1;
@@ -178,7 +178,7 @@ Carve carve(const adr_problem* p, const Geometry& g, char* base) {
 Reaction reaction_of(const adr_problem* p) {
   Reaction r{};
   r.model = p->model;
-  for (int i = 0; i < 8; ++i) r.p[i] = p->params[i];
+  for (int i = 0; i < ADR_MAX_PARAMS; ++i) r.p[i] = p->params[i];
   return r;
 }
 
@@ -657,6 +657,80 @@ int adr_device_copy(const double* in, double* out, size_t count, void* stream) {
   if (!in || !out) return ADR_EINVAL;
   if (count == 0) return ADR_OK;
   return dev_err(launch_copy_f64(in, out, count, static_cast<hipStream_t>(stream)));
+}
+
+size_t adr_indicators_workspace_bytes(int d, const int32_t* n) {
+  if (d < 1 || d > ADR_MAX_DIM || !n) return 0;
+  for (int k = 0; k < d; ++k)
+    if (n[k] < 1) return 0;
+  return align_up(sizeof(double) * 5 * kMaxIndicatorBlocks);
+}
+
+int adr_indicators(int d, const int32_t* n, const double* U, const double* V,
+                   const double* Uprev, const double* Vprev, double* rec, void* work,
+                   size_t work_bytes, void* stream) {
+  if (d < 1 || d > ADR_MAX_DIM || !n || !U || !V || !rec) return ADR_EINVAL;
+  if ((Uprev == nullptr) != (Vprev == nullptr)) return ADR_EINVAL;
+  int nn[3] = {1, 1, 1};
+  long long N = 1;
+  for (int k = 0; k < d; ++k) {
+    if (n[k] < 1) return ADR_EINVAL;
+    nn[k] = n[k];
+    N *= n[k];
+  }
+  if (N >= (1LL << 31)) return ADR_EINVAL;
+  if (!work || work_bytes < adr_indicators_workspace_bytes(d, n)) return ADR_ENOMEM;
+  return dev_err(launch_indicators(d, nn, U, V, Uprev, Vprev, static_cast<double*>(work), rec,
+                                   static_cast<hipStream_t>(stream)));
+}
+
+size_t adr_monitor_workspace_bytes(const adr_problem* p) {
+  Geometry g{};
+  if (check_problem(p, g) != ADR_OK) return 0;
+  return 2 * align_up((size_t)g.N * sizeof(double)) +
+         align_up(sizeof(double) * 5 * kMaxIndicatorBlocks);
+}
+
+int adr_solve_monitored(const adr_problem* p, double* U, double* V, int nsteps, int every,
+                        double* rec, void* work, size_t work_bytes, void* mwork,
+                        size_t mwork_bytes, void* stream) {
+  Geometry g{};
+  int st = check_problem(p, g);
+  if (st != ADR_OK) return st;
+  if (!U || !V || !rec || nsteps < 0 || every < 1) return ADR_EINVAL;
+  if (!mwork || mwork_bytes < adr_monitor_workspace_bytes(p)) return ADR_ENOMEM;
+  if (reinterpret_cast<uintptr_t>(mwork) % kAlign != 0) return ADR_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(mwork);
+  const size_t tb = align_up((size_t)g.N * sizeof(double));
+  double* Pu = reinterpret_cast<double*>(base);
+  double* Pv = reinterpret_cast<double*>(base + tb);
+  double* partial = reinterpret_cast<double*>(base + 2 * tb);
+  int nn[3] = {g.n[0], g.n[1], g.n[2]};
+  const int records = nsteps / every;
+  for (int k = 0; k < records; ++k) {
+    // every-1 plain steps, then keep C_n, take the recorded step, reduce
+    st = do_steps(p, U, V, every - 1, work, work_bytes, stream);
+    if (st != ADR_OK) return st;
+    if (launch_copy_f64(U, Pu, (size_t)g.N, s) != hipSuccess ||
+        launch_copy_f64(V, Pv, (size_t)g.N, s) != hipSuccess)
+      return ADR_EDEVICE;
+    st = do_steps(p, U, V, 1, work, work_bytes, stream);
+    if (st != ADR_OK) return st;
+    if (launch_indicators(g.d, nn, U, V, Pu, Pv, partial, rec + 5 * (size_t)k, s) != hipSuccess)
+      return ADR_EDEVICE;
+  }
+  st = do_steps(p, U, V, nsteps - records * every, work, work_bytes, stream);
+  if (st != ADR_OK || records == 0) return st;
+  // one synchronisation: was any recorded state non-finite?
+  std::vector<double> host((size_t)records * 5);
+  if (hipMemcpyAsync(host.data(), rec, host.size() * sizeof(double), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return ADR_EDEVICE;
+  for (int k = 0; k < records; ++k)
+    if (host[5 * (size_t)k + 4] != 0.0) return ADR_ENONFINITE;
+  return ADR_OK;
 }
 
 int adr_timing_enable(int capacity) {

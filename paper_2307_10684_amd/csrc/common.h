@@ -87,7 +87,7 @@ hipError_t launch_split_bf16(int n, const double* M, unsigned short* Mh, unsigne
 // Reaction model constants as passed to the stage kernels.
 struct Reaction {
   int model;
-  double p[8];
+  double p[12];
 };
 
 struct StageGeom {
@@ -149,6 +149,15 @@ hipError_t launch_lawson_stage1(long long N, const Reaction& r, double tau, cons
 // Lawson2b stage 2: C += tau/2 G^c(U2, V2)  (C holds the second Tucker result).
 hipError_t launch_lawson_stage2(long long N, const Reaction& r, double tau, double* U, double* V,
                                 const double* U2, const double* V2, hipStream_t s);
+
+// Dynamics indicators (trapezoidal means, increment norms, non-finite count)
+// into rec[0..4]; `partial` holds 5 * indicator_blocks(N) doubles.  Up and Vp
+// are both given or both null.
+constexpr int kMaxIndicatorBlocks = 2048;
+int indicator_blocks(long long N);
+hipError_t launch_indicators(int d, const int* n, const double* U, const double* V,
+                             const double* Up, const double* Vp, double* partial, double* rec,
+                             hipStream_t s);
 
 // Small dense helpers for the matrix-function precompute (n x n, column-major).
 hipError_t launch_norm1(int n, const double* X, double scale, double* out, hipStream_t s);

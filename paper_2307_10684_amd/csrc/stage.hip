@@ -28,6 +28,14 @@ __device__ __forceinline__ void react(const Reaction& r, double u, double v, dou
       gv = r.p[1] * u - u2v;
       break;
     }
+    case 4: {  // DIB: rho(a1u(1-v)u - a2u u^3 - a3u(v-a4u)),
+               //      rho(a1v(1+a2v u)(1-v)(1-a3v(1-v)) - a4v v(1+a5v u)(1+a3v v))
+      const double w = 1.0 - v;
+      gu = r.p[0] * (r.p[1] * w * u - r.p[2] * u * u * u - r.p[3] * (v - r.p[4]));
+      gv = r.p[0] * (r.p[5] * (1.0 + r.p[6] * u) * w * (1.0 - r.p[7] * w) -
+                     r.p[8] * v * (1.0 + r.p[9] * u) * (1.0 + r.p[7] * v));
+      break;
+    }
     default:
       gu = 0.0;
       gv = 0.0;

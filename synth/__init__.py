@@ -26,6 +26,8 @@ C ABI, ``include/adr.h``):
   g^u = rho*(u - u^3 - v),      g^v = rho*eps*(u - a1*v - a0)  (Sec. 4.2-4.3, eqs. (13)-(14))
 * ``brusselator``   params = (A, B):
   g^u = A - (B+1) u + u^2 v,    g^v = B u - u^2 v              (Sec. 4.6, eq. (17))
+* ``dib``           params = (rho, a1u, a2u, a3u, a4u, a1v, a2v, a3v, a4v, a5v):
+  the morpho-chemical DIB model of Sec. 4.4, eq. (15)
 
 The formulas are listed here as documentation of the parameter order only;
 each side implements them on its own.
@@ -172,6 +174,27 @@ def paper_brusselator_3d(n: int = 64, steps: int = 100, T: float = 1.0) -> Workl
         diff=(0.01, 0.02), vel_u=(0.1,) * 3, vel_v=(0.1,) * 3,
         model="brusselator", params=(2.0, 1.0), tau=T / steps, steps=steps,
         init="sine_bruss")
+
+
+def dib_a4v(a1v: float, a4u: float, a3v: float) -> float:
+    """The constant a_4^v that Sec. 4.4 chooses so that (0, a_4^u) is an
+    equilibrium of the DIB reaction (a Turing-unstable one)."""
+    return a1v * (1.0 - a4u) * (1.0 - a3v + a3v * a4u) / (a4u * (1.0 + a3v * a4u))
+
+
+def dib_2d(n: int = 200, steps: int = 1250, T: float = 2.5) -> Workload:
+    """The 2D morpho-chemical DIB experiment of Sec. 4.4 / Table 4: [0,20]^2,
+    delta^u = 1, delta^v = 20, rho = 25/4 and the constants printed there;
+    initial data (0, a_4^u) plus 1e-5 * U(0, 1) noise (seeded here; the paper
+    seeds MATLAB's generator, which this does not reproduce)."""
+    a1u, a2u, a3u, a4u = 10.0, 1.0, 66.0, 0.5
+    a1v, a2v, a3v, a5v = 3.0, 2.5, 0.2, 1.5
+    a4v = dib_a4v(a1v, a4u, a3v)
+    return Workload(
+        name=f"dib2d_{n}", n=(n, n), domain=((0.0, 20.0),) * 2,
+        diff=(1.0, 20.0), vel_u=(0.0, 0.0), vel_v=(0.0, 0.0),
+        model="dib", params=(25.0 / 4.0, a1u, a2u, a3u, a4u, a1v, a2v, a3v, a4v, a5v),
+        tau=T / steps, steps=steps, init="noise", base=(0.0, a4u), noise=(0.0, 1e-5))
 
 
 def paper_schnakenberg_3d(n: int = 80, steps: int = 50, T: float = 0.4) -> Workload:

@@ -33,7 +33,11 @@ def pytest_collection_modifyitems(config, items):
 @pytest.fixture(scope="session")
 def adr():
     """The HIP binding, built first if the library is missing."""
-    from paper_2307_10684_amd import build as _build
+    import importlib.util
+    path = os.path.join(ROOT, "paper_2307_10684_amd", "build.py")
+    spec = importlib.util.spec_from_file_location("_adr_build", path)
+    _build = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(_build)   # by path: the package import needs the library
     if not os.path.exists(_build.LIB):
         _build.build()
     import paper_2307_10684_amd

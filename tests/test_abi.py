@@ -189,3 +189,30 @@ def test_batch_create_validates_before_device_work(adr):
     assert lib.adr_batch_info(None, None, 0, None) == adr.ADR_EINVAL
     assert lib.adr_batch_destroy(None) == adr.ADR_EINVAL
     assert lib.adr_batch_create(1, None, None, None, None, None, 0, None, None) == adr.ADR_EINVAL
+
+
+def test_indicator_entry_points_validate(adr):
+    lib = adr._lib
+    n3 = (ctypes.c_int32 * 3)(4, 4, 4)
+    wb = adr.adr_indicators_workspace_bytes((4, 4, 4))
+    assert wb >= 5 * 8
+    assert lib.adr_indicators(0, n3, 4096, 4096, None, None, 4096, 4096, wb, None) == adr.ADR_EINVAL
+    assert lib.adr_indicators(3, n3, None, 4096, None, None, 4096, 4096, wb, None) == adr.ADR_EINVAL
+    # both previous states or neither
+    assert lib.adr_indicators(3, n3, 4096, 4096, 4096, None, 4096, 4096, wb, None) == adr.ADR_EINVAL
+    assert lib.adr_indicators(3, n3, 4096, 4096, None, None, 4096, 4096, 8, None) == adr.ADR_ENOMEM
+    p = _problem(adr)
+    mb = adr.adr_monitor_workspace_bytes(p)
+    assert mb >= 2 * 8 ** 3 * 8
+    st = lib.adr_solve_monitored(ctypes.byref(p), 4096, 4096, 4, 0, 4096, 4096, 1 << 30, 4096,
+                                 mb, None)
+    assert st == adr.ADR_EINVAL                      # every < 1
+    st = lib.adr_solve_monitored(ctypes.byref(p), 4096, 4096, 4, 1, None, 4096, 1 << 30, 4096,
+                                 mb, None)
+    assert st == adr.ADR_EINVAL                      # no record buffer
+    st = lib.adr_solve_monitored(ctypes.byref(p), 4096, 4096, 4, 1, 4096, 4096, 1 << 30, 4096,
+                                 mb - 8, None)
+    assert st == adr.ADR_ENOMEM
+    st = lib.adr_solve_monitored(ctypes.byref(p), 4096, 4096, 4, 1, 4096, 4096, 1 << 30, 4097,
+                                 mb, None)
+    assert st == adr.ADR_EINVAL                      # misaligned monitor workspace

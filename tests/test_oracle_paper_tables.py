@@ -1,4 +1,4 @@
-"""Weak pins of the whole oracle against the errors printed in Table 6 (Sec. 4.6).
+"""Weak pins of the whole oracle against the errors printed in Tables 4 and 6.
 
 The advective Brusselator experiment has deterministic initial data, so the
 oracle can rerun it: 64^3 grid, T = 1, errors of ETD2RKds and Lawson2b against
@@ -49,3 +49,26 @@ def test_table6_all_rows(scheme):
     for got, want in zip(errs, row["error"]):
         assert got == pytest.approx(want, rel=0.01)
     assert np.allclose(np.round(O.observed_order(row["steps"], errs), 2), row["order"], atol=0.02)
+
+
+@pytest.mark.slow
+def test_table4_dib_etd2rkds():
+    """Sec. 4.4 / Table 4: DIB model on 200^2, T = 2.5.  The paper's noise comes
+    from MATLAB's generator (seed 123), which is not reproduced; with seeded
+    noise of the same law the errors agree to within 10% and the orders to
+    0.05 (measured: 1.18e-2, 8.12e-3, 5.94e-3, 4.53e-3; orders 2.03)."""
+    row = TAB["table4_dib2d"]["etd2rkds"]
+
+    def run(steps):
+        w = S.dib_2d(200, steps)
+        p = O.problem_from_workload(w)
+        U0, V0 = S.initial_state(w, 123)
+        return O.solve(U0, V0, p, steps)
+
+    U1, V1 = run(4000)
+    U2, V2 = run(8000)
+    Ur, Vr = (4 * U2 - U1) / 3, (4 * V2 - V1) / 3
+    errs = [O.relative_error(*run(s), Ur, Vr) for s in row["steps"]]
+    for got, want in zip(errs, row["error"]):
+        assert got == pytest.approx(want, rel=0.10)
+    assert np.allclose(O.observed_order(row["steps"], errs), row["order"], atol=0.05)
