@@ -304,7 +304,7 @@ int adr_batch_create(int count, const adr_problem* problems, double* const* U, d
     j.R[0] = b->carves[i].R[0];
     j.R[1] = b->carves[i].R[1];
     int gz;
-    const int nb = stage1_blocks(j.g, j.gx, j.gy, gz);
+    const int nb = stage1_plan(j.g, j.kind, j.gx, j.gy, gz);
     j.block_begin = blocks;
     blocks += nb;
     PointJob& q = s2[i];

@@ -98,13 +98,15 @@ struct StageGeom {
 };
 
 // Grouped stage launches over several problems (batched and serving runs).
+constexpr int kStage1Point = 0, kStage1Tile = 1;   // stage-1 kernel variants
 struct StageJob {
   StageGeom g;
   Reaction r;
+  int kind;                // kStage1Point or kStage1Tile (from stage1_plan)
   const double* U;
   const double* V;
   void* R[2];
-  int gx, gy;              // block grid of this problem (x: i1/64, y: i2/4, z: planes)
+  int gx, gy;              // block grid of this problem (from stage1_plan)
   long long block_begin;   // first block of this problem in the grouped launch
 };
 struct PointJob {
@@ -124,7 +126,8 @@ hipError_t launch_stage1_grouped(const StageJob* jobs, int njobs, long long nblo
                                  hipStream_t s);
 hipError_t launch_pointwise_grouped(const PointJob* jobs, int njobs, long long nblocks, int r_f32,
                                     hipStream_t s);
-int stage1_blocks(const StageGeom& g, int& gx, int& gy, int& gz);
+// Stage-1 variant and block grid of one problem (gx * gy * gz blocks of 64 x 4).
+int stage1_plan(const StageGeom& g, int& kind, int& gx, int& gy, int& gz);
 
 // ETD2RKds stage 1: R^c = sum_mu C x_mu A_mu^c (stencil where a band is given,
 // nothing where it is not) + G^c(U, V).  R may be FP64 or FP32.

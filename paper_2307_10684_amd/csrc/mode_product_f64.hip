@@ -282,9 +282,9 @@ __global__ __launch_bounds__(64 * WI * WX, 2) void k_mode_f64_grouped(const Tile
 // loads move two doubles per lane, and the first k-chunk of the next tile is
 // fetched while the last chunk of the current one is multiplied, so tile
 // boundaries (epilogue stores, first loads) overlap with MFMA work.
-template <int BI, int BX, int WI, int WX, int BK, bool KFAST>
-__global__ __launch_bounds__(64 * WI * WX, 2) void k_mode_f64_persist(ModeArgs a, int n_itiles,
-                                                                     int n_xtiles, int ntiles) {
+template <int BI, int BX, int WI, int WX, int BK, bool KFAST, int MINB = 2>
+__global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64_persist(ModeArgs a, int n_itiles,
+                                                                        int n_xtiles, int ntiles) {
   constexpr int NT = 64 * WI * WX;
   constexpr int TI = BI / WI, TX = BX / WX;
   constexpr int FI = TI / 16, FX = TX / 16;
@@ -608,7 +608,10 @@ hipError_t launch_mode_product_f64(const ModeArgs& a, hipStream_t s) {
     if (launch_persist<64, 128, 1, 4, 16>(a, s, e)) return e;
     return launch_cfg<64, 128, 1, 4, 16>(a, s);
   }
-  if (launch_persist<128, 128, 2, 2, 16>(a, s, e)) return e;
+  // fibre-contiguous products (L = 1) run best with a 2 x 4 wave grid (64 x 32
+  // per wave), the others with 2 x 2 (64 x 64 per wave), measured at 256^3
+  if (a.L == 1 && launch_persist<128, 128, 2, 4, 16>(a, s, e)) return e;
+  if (a.L != 1 && launch_persist<128, 128, 2, 2, 16>(a, s, e)) return e;
   return launch_cfg<128, 128, 2, 2, 16>(a, s);
 }
 

@@ -49,42 +49,212 @@ __device__ __forceinline__ void put(void* p, long long q, double x) {
 
 // Stage 1: R^c = sum_mu (C x_mu A_mu^c) + G^c(U, V) for the directions with a
 // band; directions without one are added afterwards by dense mode products.
-// Block = (64, 4) threads over (i_1, i_2); each block marches through kZB planes
-// of i_3.  A plane's centre value is loaded once: it serves as the i_3 + 1
-// neighbour of the plane before, then as the centre, then as the i_3 - 1
-// neighbour.  Inside a wave the i_1 +- 1 neighbours come from lane shuffles
-// (the wave-edge lanes load theirs); the i_2 +- 1 neighbours are loads that
-// the neighbouring rows of the block have just brought into the L1 cache.
-// Loads are branch-free (clamped index, then masked).  Latency is hidden by
-// occupancy: the kernel keeps few registers so that many waves share a SIMD.
-constexpr int kZB = 16;  // planes per block
+// Two kernels: an LDS-tiled plane march for large grids and a one-plane-per-
+// block kernel for small ones (stage1_plan picks by the problem's own size).
+// Loads are branch-free (clamped index, then masked); outside the grid the
+// neighbour is taken as 0, where the band coefficient is 0 as well.
 
-template <typename TR>
-__device__ __forceinline__ void etd_stage1_block(const StageGeom& g, const Reaction& r,
-                                                 const double* __restrict__ U,
-                                                 const double* __restrict__ V, void* Ru,
-                                                 void* Rv, int bx, int by, int bz) {
+// Workgroups are dealt to the 8 XCDs round-robin by linear dispatch index, and
+// each XCD has its own L2.  Remapping linear index b to (b % 8) * (G / 8) + b / 8
+// gives each XCD a contiguous range of tiles, so the halo rows and planes that
+// neighbouring tiles share are mostly fetched once into one L2.
+__device__ __forceinline__ void xcd_block(int& bx, int& by, int& bz) {
+  const unsigned gx = gridDim.x, gy = gridDim.y, G = gx * gy * gridDim.z;
+  unsigned b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  if (G % 8u == 0u) b = (b % 8u) * (G / 8u) + b / 8u;
+  bx = (int)(b % gx);
+  b /= gx;
+  by = (int)(b % gy);
+  bz = (int)(b / gy);
+}
+
+// Stage 1 on LDS tiles.  A block of 64 x 4 threads owns a tile of kTX = 64
+// values of i_1 by kTY = 16 rows of i_2 and marches through ZB planes of i_3.
+// The plane being computed sits in LDS with a one-point halo in i_1 and i_2
+// (zero outside the grid, where the band coefficient is zero too); its i_3
+// neighbours are the previous and next planes' values of the thread's own
+// points, held in registers.  The loads of the plane after next are issued
+// before the current plane is computed, so the compute of one plane covers
+// the memory latency of the loads for a later one.  Every value of the tile is
+// read from HBM once per plane; halos come from neighbouring tiles (L2).
+constexpr int kTX = 64, kTY = 16, kRows = kTY / 4;
+constexpr int kZB = 8;   // planes per block of the tiled kernel
+
+template <typename TR, int ZB>
+__device__ __forceinline__ void etd_stage1_tile(const StageGeom& g, const Reaction& r,
+                                                const double* __restrict__ U,
+                                                const double* __restrict__ V, void* Ru, void* Rv,
+                                                int bx, int by, int bz) {
   const int n1 = g.n[0], n2 = g.d >= 2 ? g.n[1] : 1, n3 = g.d >= 3 ? g.n[2] : 1;
-  const int i1 = bx * 64 + threadIdx.x;
-  // i_2 is the same on the whole wave (blockDim.x = 64): keep it in a scalar
-  // register so its band coefficients are scalar loads
-  const int i2 = __builtin_amdgcn_readfirstlane(by * 4 + threadIdx.y);
-  const int z0 = bz * kZB;
-  const int z1 = min(z0 + kZB, n3);
-  const bool live = i1 < n1 && i2 < n2;
-  const unsigned P = (unsigned)n1 * (unsigned)n2;  // plane stride
-  const int lane = threadIdx.x;
-  const int tid = threadIdx.y * 64 + threadIdx.x;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
+  const int x0 = bx * kTX, y0 = by * kTY;
+  const int z0 = bz * ZB, z1 = min(z0 + ZB, n3);
+  const unsigned P = (unsigned)n1 * (unsigned)n2;
 
-  // i_3 band coefficients of this block's planes (zero without a band)
-  __shared__ double sb3[2][3][kZB];
-  if (tid < 2 * 3 * kZB) {
-    const int c = tid / (3 * kZB), j = (tid / kZB) % 3, zz = tid % kZB, z = z0 + zz;
+  __shared__ double sU[kTY + 2][kTX + 2];
+  __shared__ double sV[kTY + 2][kTX + 2];
+  __shared__ double sb2[2][3][kTY];
+  __shared__ double sb3[2][3][ZB];
+
+  // band coefficients of directions 2 and 3 for this tile (zero without a band)
+  if (tid < 2 * 3 * kTY) {
+    const int c = tid / (3 * kTY), j = (tid / kTY) % 3, yy = tid % kTY, y = y0 + yy;
+    const double* b = g.d >= 2 ? g.band[c][1] : nullptr;
+    sb2[c][j][yy] = (b && y < n2) ? b[j * n2 + y] : 0.0;
+  }
+  if (tid < 2 * 3 * ZB) {
+    const int c = tid / (3 * ZB), j = (tid / ZB) % 3, zz = tid % ZB, z = z0 + zz;
     const double* b = g.d >= 3 ? g.band[c][2] : nullptr;
     sb3[c][j][zz] = (b && z < n3) ? b[j * n3 + z] : 0.0;
   }
-  // per-thread band coefficients of directions 1 and 2
+  const int i1 = x0 + tx;
+  const bool col_ok = i1 < n1;
+  double a1u[3] = {0, 0, 0}, a1v[3] = {0, 0, 0};
+  if (col_ok) {
+    if (g.band[0][0]) for (int j = 0; j < 3; ++j) a1u[j] = g.band[0][0][j * n1 + i1];
+    if (g.band[1][0]) for (int j = 0; j < 3; ++j) a1v[j] = g.band[1][0][j * n1 + i1];
+  }
+
+  // this thread's points: column i1, rows y0 + ty + 4k; in-plane offsets
+  bool pt_ok[kRows];
+  unsigned pt_off[kRows];
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) {
+    const int i2 = y0 + ty + 4 * k;
+    pt_ok[k] = col_ok && i2 < n2;
+    pt_off[k] = pt_ok[k] ? (unsigned)i2 * (unsigned)n1 + (unsigned)i1 : 0u;
+  }
+  // halo point of this thread (threads 0..159): rows above/below, columns left/right
+  int h_r = 0, h_c = 0;
+  bool h_ok = false;
+  unsigned h_off = 0;
+  if (tid < 2 * kTX + 2 * kTY) {
+    int hx, hy;
+    if (tid < kTX) { hx = x0 + tid; hy = y0 - 1; h_r = 0; h_c = tid + 1; }
+    else if (tid < 2 * kTX) { hx = x0 + tid - kTX; hy = y0 + kTY; h_r = kTY + 1; h_c = tid - kTX + 1; }
+    else if (tid < 2 * kTX + kTY) { hx = x0 - 1; hy = y0 + tid - 2 * kTX; h_r = tid - 2 * kTX + 1; h_c = 0; }
+    else { hx = x0 + kTX; hy = y0 + tid - 2 * kTX - kTY; h_r = tid - 2 * kTX - kTY + 1; h_c = kTX + 1; }
+    h_ok = hx >= 0 && hx < n1 && hy >= 0 && hy < n2;
+    h_off = h_ok ? (unsigned)hy * (unsigned)n1 + (unsigned)hx : 0u;
+  }
+  const bool has_halo = tid < 2 * kTX + 2 * kTY;
+
+  // plane loads (clamped index, masked afterwards)
+  auto load_plane = [&](int z, double (&iu)[kRows], double (&iv)[kRows], double& hu, double& hv) {
+    const bool zok = z >= 0 && z < n3;
+    const unsigned base = zok ? (unsigned)z * P : 0u;
+    double lu[kRows], lv[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      lu[k] = U[base + pt_off[k]];
+      lv[k] = V[base + pt_off[k]];
+    }
+    const double a = U[base + h_off], b = V[base + h_off];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      iu[k] = (zok && pt_ok[k]) ? lu[k] : 0.0;
+      iv[k] = (zok && pt_ok[k]) ? lv[k] : 0.0;
+    }
+    hu = (zok && h_ok) ? a : 0.0;
+    hv = (zok && h_ok) ? b : 0.0;
+  };
+  auto to_lds = [&](const double (&iu)[kRows], const double (&iv)[kRows], double hu, double hv) {
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      sU[ty + 4 * k + 1][tx + 1] = iu[k];
+      sV[ty + 4 * k + 1][tx + 1] = iv[k];
+    }
+    if (has_halo) {
+      sU[h_r][h_c] = hu;
+      sV[h_r][h_c] = hv;
+    }
+  };
+
+  double pu[kRows], pv[kRows], cu[kRows], cv[kRows], nu[kRows], nv[kRows];
+  double hcu, hcv, hnu, hnv, dummy_u, dummy_v;
+  load_plane(z0 - 1, pu, pv, dummy_u, dummy_v);
+  load_plane(z0, cu, cv, hcu, hcv);
+  load_plane(z0 + 1, nu, nv, hnu, hnv);
+  to_lds(cu, cv, hcu, hcv);
+  __syncthreads();
+
+  for (int z = z0; z < z1; ++z) {
+    // loads of plane z + 2, in flight during this plane's compute
+    double lu[kRows], lv[kRows], lhu, lhv;
+    const bool more = z + 1 < z1;
+    if (more) load_plane(z + 2, lu, lv, lhu, lhv);
+    const int zz = z - z0;
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const int ly = ty + 4 * k + 1, lx = tx + 1;
+      const double uc = cu[k], vc = cv[k];
+      const double um = sU[ly][lx - 1], uq = sU[ly][lx + 1];
+      const double vm = sV[ly][lx - 1], vq = sV[ly][lx + 1];
+      const double uym = sU[ly - 1][lx], uyp = sU[ly + 1][lx];
+      const double vym = sV[ly - 1][lx], vyp = sV[ly + 1][lx];
+      const int yy = ty + 4 * k;
+      double gu, gv;
+      react(r, uc, vc, gu, gv);
+      double ku = a1u[0] * um + a1u[1] * uc + a1u[2] * uq;
+      double kv = a1v[0] * vm + a1v[1] * vc + a1v[2] * vq;
+      ku += sb2[0][0][yy] * uym + sb2[0][1][yy] * uc + sb2[0][2][yy] * uyp;
+      kv += sb2[1][0][yy] * vym + sb2[1][1][yy] * vc + sb2[1][2][yy] * vyp;
+      ku += sb3[0][0][zz] * pu[k] + sb3[0][1][zz] * uc + sb3[0][2][zz] * nu[k];
+      kv += sb3[1][0][zz] * pv[k] + sb3[1][1][zz] * vc + sb3[1][2][zz] * nv[k];
+      if (pt_ok[k]) {
+        const unsigned q = (unsigned)z * P + pt_off[k];
+        put<TR>(Ru, q, ku + gu);
+        put<TR>(Rv, q, kv + gv);
+      }
+    }
+    if (!more) break;
+    __syncthreads();          // everyone is done with plane z in LDS
+    to_lds(nu, nv, hnu, hnv);  // plane z + 1
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      pu[k] = cu[k];
+      pv[k] = cv[k];
+      cu[k] = nu[k];
+      cv[k] = nv[k];
+      nu[k] = lu[k];
+      nv[k] = lv[k];
+    }
+    hnu = lhu;
+    hnv = lhv;
+  }
+}
+
+// Stage 1, one plane per block: every load of a thread is independent and
+// issued at once (no marching), so latency is hidden by the many waves a CU
+// holds at this kernel's small register footprint.  i_1 neighbours come from
+// lane shuffles; i_2 and i_3 neighbours are loads that mostly hit L1/L2 (the
+// neighbouring rows and planes are loaded by neighbouring blocks of the same
+// XCD at about the same time).
+template <typename TR>
+__device__ __forceinline__ void etd_stage1_point(const StageGeom& g, const Reaction& r,
+                                                 const double* __restrict__ U,
+                                                 const double* __restrict__ V, void* Ru, void* Rv,
+                                                 int bx, int by, int z) {
+  const int n1 = g.n[0], n2 = g.d >= 2 ? g.n[1] : 1, n3 = g.d >= 3 ? g.n[2] : 1;
+  const int lane = threadIdx.x;
+  const int i1 = bx * 64 + lane;
+  const int i2 = __builtin_amdgcn_readfirstlane(by * 4 + threadIdx.y);
+  const bool live = i1 < n1 && i2 < n2;
+  const unsigned P = (unsigned)n1 * (unsigned)n2;
+  const unsigned q = live ? (unsigned)z * P + (unsigned)i2 * (unsigned)n1 + (unsigned)i1 : 0u;
+  const bool okm2 = live && i2 > 0, okp2 = live && i2 + 1 < n2;
+  const bool okm3 = live && z > 0, okp3 = live && z + 1 < n3;
+  const bool edm = live && lane == 0 && i1 > 0, edp = live && lane == 63 && i1 + 1 < n1;
+  const unsigned qym = okm2 ? q - n1 : 0u, qyp = okp2 ? q + n1 : 0u;
+  const unsigned qzm = okm3 ? q - P : 0u, qzp = okp3 ? q + P : 0u;
+  const unsigned qxm = edm ? q - 1 : 0u, qxp = edp ? q + 1 : 0u;
+  const double l_u = U[q], l_v = V[q];
+  const double l_uym = U[qym], l_uyp = U[qyp], l_vym = V[qym], l_vyp = V[qyp];
+  const double l_uzm = U[qzm], l_uzp = U[qzp], l_vzm = V[qzm], l_vzp = V[qzp];
+  const double l_uxm = U[qxm], l_uxp = U[qxp], l_vxm = V[qxm], l_vxp = V[qxp];
   double a1u[3] = {0, 0, 0}, a1v[3] = {0, 0, 0}, a2u[3] = {0, 0, 0}, a2v[3] = {0, 0, 0};
+  double a3u[3] = {0, 0, 0}, a3v[3] = {0, 0, 0};
   if (live) {
     if (g.band[0][0]) for (int j = 0; j < 3; ++j) a1u[j] = g.band[0][0][j * n1 + i1];
     if (g.band[1][0]) for (int j = 0; j < 3; ++j) a1v[j] = g.band[1][0][j * n1 + i1];
@@ -93,77 +263,62 @@ __device__ __forceinline__ void etd_stage1_block(const StageGeom& g, const React
     if (g.band[0][1]) for (int j = 0; j < 3; ++j) a2u[j] = g.band[0][1][j * n2 + i2];
     if (g.band[1][1]) for (int j = 0; j < 3; ++j) a2v[j] = g.band[1][1][j * n2 + i2];
   }
-  __syncthreads();
-  const bool has_m2 = live && i2 > 0, has_p2 = live && i2 + 1 < n2;
-  const bool edge_m = live && lane == 0 && i1 > 0;
-  const bool edge_p = live && lane == 63 && i1 + 1 < n1;
-  const unsigned q0 = (unsigned)i2 * (unsigned)n1 + (unsigned)i1;
-
-  double pu, pv, uc, vc;  // centres of planes z-1 and z
-  {
-    const bool okp = live && z0 > 0;
-    const unsigned qp = okp ? q0 + (unsigned)(z0 - 1) * P : 0u;
-    const unsigned qc = live ? q0 + (unsigned)z0 * P : 0u;
-    const double a = U[qp], b = V[qp], c = U[qc], d = V[qc];
-    pu = okp ? a : 0.0;
-    pv = okp ? b : 0.0;
-    uc = live ? c : 0.0;
-    vc = live ? d : 0.0;
+  if (g.d >= 3) {
+    if (g.band[0][2]) for (int j = 0; j < 3; ++j) a3u[j] = g.band[0][2][j * n3 + z];
+    if (g.band[1][2]) for (int j = 0; j < 3; ++j) a3v[j] = g.band[1][2][j * n3 + z];
   }
-  for (int z = z0; z < z1; ++z) {
-    const unsigned q = q0 + (unsigned)z * P;
-    const bool has_n3 = z + 1 < n3;
-    const bool okn = live && has_n3;
-    const unsigned qn = okn ? q + P : 0u;
-    const unsigned qym = has_m2 ? q - n1 : 0u, qyp = has_p2 ? q + n1 : 0u;
-    const unsigned qxm = edge_m ? q - 1 : 0u, qxp = edge_p ? q + 1 : 0u;
-    const double l_un = U[qn], l_vn = V[qn];
-    const double l_uym = U[qym], l_uyp = U[qyp], l_vym = V[qym], l_vyp = V[qyp];
-    const double l_uxm = U[qxm], l_uxp = U[qxp], l_vxm = V[qxm], l_vxp = V[qxp];
-    const double un = okn ? l_un : 0.0, vn = okn ? l_vn : 0.0;
-    // i_1 neighbours from the adjacent lanes (the edge lanes use their loads)
-    double um = __shfl_up(uc, 1, 64), uq = __shfl_down(uc, 1, 64);
-    double vm = __shfl_up(vc, 1, 64), vq = __shfl_down(vc, 1, 64);
-    if (lane == 0) {
-      um = edge_m ? l_uxm : 0.0;
-      vm = edge_m ? l_vxm : 0.0;
-    }
-    if (lane == 63) {
-      uq = edge_p ? l_uxp : 0.0;
-      vq = edge_p ? l_vxp : 0.0;
-    }
-    const double uym = has_m2 ? l_uym : 0.0, uyp = has_p2 ? l_uyp : 0.0;
-    const double vym = has_m2 ? l_vym : 0.0, vyp = has_p2 ? l_vyp : 0.0;
-    if (live) {
-      const int zz = z - z0;
-      double gu, gv;
-      react(r, uc, vc, gu, gv);
-      double ku = a1u[0] * um + a1u[1] * uc + a1u[2] * uq;
-      double kv = a1v[0] * vm + a1v[1] * vc + a1v[2] * vq;
-      ku += a2u[0] * uym + a2u[1] * uc + a2u[2] * uyp;
-      kv += a2v[0] * vym + a2v[1] * vc + a2v[2] * vyp;
-      ku += sb3[0][0][zz] * pu + sb3[0][1][zz] * uc + sb3[0][2][zz] * un;
-      kv += sb3[1][0][zz] * pv + sb3[1][1][zz] * vc + sb3[1][2][zz] * vn;
-      put<TR>(Ru, q, ku + gu);
-      put<TR>(Rv, q, kv + gv);
-    }
-    pu = uc;
-    pv = vc;
-    uc = un;
-    vc = vn;
+  const double uc = live ? l_u : 0.0, vc = live ? l_v : 0.0;
+  double um = __shfl_up(uc, 1, 64), uq = __shfl_down(uc, 1, 64);
+  double vm = __shfl_up(vc, 1, 64), vq = __shfl_down(vc, 1, 64);
+  if (lane == 0) {
+    um = edm ? l_uxm : 0.0;
+    vm = edm ? l_vxm : 0.0;
   }
+  if (lane == 63) {
+    uq = edp ? l_uxp : 0.0;
+    vq = edp ? l_vxp : 0.0;
+  }
+  if (!live) return;
+  const double uym = okm2 ? l_uym : 0.0, uyp = okp2 ? l_uyp : 0.0;
+  const double vym = okm2 ? l_vym : 0.0, vyp = okp2 ? l_vyp : 0.0;
+  const double uzm = okm3 ? l_uzm : 0.0, uzp = okp3 ? l_uzp : 0.0;
+  const double vzm = okm3 ? l_vzm : 0.0, vzp = okp3 ? l_vzp : 0.0;
+  double gu, gv;
+  react(r, uc, vc, gu, gv);
+  double ku = a1u[0] * um + a1u[1] * uc + a1u[2] * uq;
+  double kv = a1v[0] * vm + a1v[1] * vc + a1v[2] * vq;
+  ku += a2u[0] * uym + a2u[1] * uc + a2u[2] * uyp;
+  kv += a2v[0] * vym + a2v[1] * vc + a2v[2] * vyp;
+  ku += a3u[0] * uzm + a3u[1] * uc + a3u[2] * uzp;
+  kv += a3v[0] * vzm + a3v[1] * vc + a3v[2] * vzp;
+  put<TR>(Ru, q, ku + gu);
+  put<TR>(Rv, q, kv + gv);
 }
 
 template <typename TR>
-__global__ __launch_bounds__(256) void k_etd_stage1(StageGeom g, Reaction r,
-                                                    const double* __restrict__ U,
-                                                    const double* __restrict__ V, void* Ru,
-                                                    void* Rv) {
-  etd_stage1_block<TR>(g, r, U, V, Ru, Rv, blockIdx.x, blockIdx.y, blockIdx.z);
+__global__ __launch_bounds__(256) void k_etd_stage1_point(StageGeom g, Reaction r,
+                                                          const double* __restrict__ U,
+                                                          const double* __restrict__ V, void* Ru,
+                                                          void* Rv) {
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  etd_stage1_point<TR>(g, r, U, V, Ru, Rv, bx, by, bz);
+}
+
+template <typename TR, int ZB>
+__global__ __launch_bounds__(256) void k_etd_stage1_tile(StageGeom g, Reaction r,
+                                                         const double* __restrict__ U,
+                                                         const double* __restrict__ V, void* Ru,
+                                                         void* Rv) {
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  etd_stage1_tile<TR, ZB>(g, r, U, V, Ru, Rv, bx, by, bz);
 }
 
 // Grouped stage 1 over several problems: job j owns blocks
-// [jobs[j].block_begin, jobs[j+1].block_begin), laid out as gx * gy * gz.
+// [jobs[j].block_begin, jobs[j+1].block_begin), laid out as gx * gy * gz, and
+// runs the kernel variant its own size selects (kind), so a problem computes
+// the same values alone and in any mix.
 template <typename TR>
 __global__ __launch_bounds__(256) void k_etd_stage1_grouped(const StageJob* __restrict__ jobs,
                                                             int njobs) {
@@ -176,7 +331,10 @@ __global__ __launch_bounds__(256) void k_etd_stage1_grouped(const StageJob* __re
   const StageJob& j = jobs[lo];
   const int local = (int)(b - j.block_begin);
   const int bx = local % j.gx, rest = local / j.gx;
-  etd_stage1_block<TR>(j.g, j.r, j.U, j.V, j.R[0], j.R[1], bx, rest % j.gy, rest / j.gy);
+  if (j.kind == kStage1Tile)
+    etd_stage1_tile<TR, kZB>(j.g, j.r, j.U, j.V, j.R[0], j.R[1], bx, rest % j.gy, rest / j.gy);
+  else
+    etd_stage1_point<TR>(j.g, j.r, j.U, j.V, j.R[0], j.R[1], bx, rest % j.gy, rest / j.gy);
 }
 
 // Grouped pointwise stages: job j owns blocks [block_begin, next block_begin) of
@@ -327,17 +485,32 @@ unsigned stream_grid(long long N) {
 
 }  // namespace
 
+int stage1_plan(const StageGeom& g, int& kind, int& gx, int& gy, int& gz) {
+  const int n2 = g.d >= 2 ? g.n[1] : 1, n3 = g.d >= 3 ? g.n[2] : 1;
+  kind = (g.N >= (1LL << 20) && g.d >= 2) ? kStage1Tile : kStage1Point;
+  gx = (g.n[0] + 63) / 64;
+  gy = kind == kStage1Tile ? (n2 + kTY - 1) / kTY : (n2 + 3) / 4;
+  gz = kind == kStage1Tile ? (n3 + kZB - 1) / kZB : n3;
+  return gx * gy * gz;
+}
+
 hipError_t launch_etd_stage1(const StageGeom& g, const Reaction& r, const double* U,
                              const double* V, void* Ru, void* Rv, int r_f32, hipStream_t s) {
-  const int n2 = g.d >= 2 ? g.n[1] : 1, n3 = g.d >= 3 ? g.n[2] : 1;
-  const dim3 grid((unsigned)((g.n[0] + 63) / 64), (unsigned)((n2 + 3) / 4),
-                  (unsigned)((n3 + kZB - 1) / kZB));
-  if (grid.y > 65535 || grid.z > 65535) return hipErrorInvalidValue;
-  const dim3 block(64, 4);
-  if (r_f32)
-    hipLaunchKernelGGL(k_etd_stage1<float>, grid, block, 0, s, g, r, U, V, Ru, Rv);
-  else
-    hipLaunchKernelGGL(k_etd_stage1<double>, grid, block, 0, s, g, r, U, V, Ru, Rv);
+  int kind, gx, gy, gz;
+  stage1_plan(g, kind, gx, gy, gz);
+  if (gy > 65535 || gz > 65535) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)gz), block(64, 4);
+  if (kind == kStage1Tile) {
+    if (r_f32)
+      hipLaunchKernelGGL((k_etd_stage1_tile<float, kZB>), grid, block, 0, s, g, r, U, V, Ru, Rv);
+    else
+      hipLaunchKernelGGL((k_etd_stage1_tile<double, kZB>), grid, block, 0, s, g, r, U, V, Ru, Rv);
+  } else {
+    if (r_f32)
+      hipLaunchKernelGGL(k_etd_stage1_point<float>, grid, block, 0, s, g, r, U, V, Ru, Rv);
+    else
+      hipLaunchKernelGGL(k_etd_stage1_point<double>, grid, block, 0, s, g, r, U, V, Ru, Rv);
+  }
   return hipGetLastError();
 }
 
@@ -406,14 +579,6 @@ hipError_t launch_pointwise_grouped(const PointJob* jobs, int njobs, long long n
   else
     hipLaunchKernelGGL(k_pointwise_grouped<double>, dim3((unsigned)nblocks), dim3(256), 0, s, jobs, njobs);
   return hipGetLastError();
-}
-
-int stage1_blocks(const StageGeom& g, int& gx, int& gy, int& gz) {
-  const int n2 = g.d >= 2 ? g.n[1] : 1, n3 = g.d >= 3 ? g.n[2] : 1;
-  gx = (g.n[0] + 63) / 64;
-  gy = (n2 + 3) / 4;
-  gz = (n3 + kZB - 1) / kZB;
-  return gx * gy * gz;
 }
 
 hipError_t launch_copy_f64(const double* in, double* out, size_t count, hipStream_t s) {

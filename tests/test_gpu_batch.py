@@ -31,6 +31,8 @@ MIX = [
     S.with_shape(S.brusselator_3d(), (300,)),
     S.with_shape(S.fhn_3d(), (3, 3, 3)),
     S.with_shape(S.brusselator_3d(), (72, 40, 150)),
+    # over 2^20 points: its stage 1 takes the LDS-tiled kernel inside the grouped launch
+    S.with_shape(S.schnakenberg_2d(), (1100, 960)),
 ]
 STEPS = 6
 
