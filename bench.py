@@ -160,19 +160,20 @@ def _batched_leg(adr, S, torch, steps, seed):
 
 def _serving_leg(S, count, rate, budget_gib, seed):
     """The serving stream: Poisson arrivals of mixed 2D/3D requests, served by the
-    continuous-batching engine and, for comparison, one at a time by the plain
-    FP64 path, on the same arrival times."""
+    continuous-batching engine (second of two passes over the stream) and, for
+    comparison, one at a time by the plain FP64 path, on the same arrival
+    times."""
     from paper_2307_10684_amd import serving
     reqs = S.serving_stream(count, rate, seed)
     payload = {r.rid: S.initial_state(r.workload, r.seed) for r in reqs}
     jobs = [serving.Job(r.rid, r.arrival, r.workload, r.workload.steps,
                         lambda k=r.rid: payload[k]) for r in reqs]
     be = serving.GpuBackend("f64")
-    # warm the set-up path once (first use of the matrix-function kernels)
-    serving.Engine(be, budget_bytes=budget_gib << 30).run(
-        [serving.Job(-1, 0.0, jobs[0].workload, 2, jobs[0].initial)])
     eng = serving.Engine(be, budget_bytes=budget_gib << 30, max_active=64, max_chunk=16,
                          lane_bounds=(4e9,), keep_results=True)
+    # one untimed pass of the same stream first: device allocations, the
+    # matrix-function scratch and the plan-table pool reach their steady sizes
+    eng.run(jobs)
     eng.run(jobs)
     _, seq = serving.run_sequential(be, jobs, keep_results=True)
     keys = ("p50_latency_s", "p99_latency_s", "throughput", "makespan_s", "mean_wait_s",
