@@ -68,6 +68,26 @@ def _traffic_from_profiles(precision: str, workload: str):
         return None
 
 
+def _stage_traffic_from_profiles(workload: str):
+    """Average HBM bytes per launch of the two FP64 stage kernels from the committed
+    counter summary, or None (no summary, or stage.hip changed since)."""
+    path = os.path.join(ROOT, "profiles", f"stage_kernels_{workload}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != _src_hash("stage.hip"):
+        return None
+    try:
+        return 0.5 * (float(vals["k_etd_stage1_tile_hbm_bytes_per_launch"]) +
+                      float(vals["k_etd_stage2_hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(workload, steps: int = 2):
     """The oracle as it stands, timed on the host for a bounded number of steps."""
     import numpy as np
@@ -344,7 +364,11 @@ def main(argv=None):
             "achieved": stage_bytes / (stage_avg_ms * 1e-3) / 1e9,
             "peak": PEAKS["hbm_gbs"],
             "unit": "GB/s",
+            "frac": stage_bytes / (stage_avg_ms * 1e-3) / 1e9 / PEAKS["hbm_gbs"],
             "launches": n_stage,
+            "algorithmic_bytes_per_launch": stage_bytes,
+            "traffic": (_stage_traffic_from_profiles(w.name)
+                        if args.precision == "f64" and args.scheme == "etd2rkds" else None),
         },
         "timing_pass_ms_per_step": 1e3 * elapsed_ev / args.steps,
         "finite": finite,
