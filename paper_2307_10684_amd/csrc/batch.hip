@@ -33,6 +33,7 @@ struct ModePhase {
   // one job table per tile configuration (tile offsets depend on the tile shape)
   TileJob* jobs[kNumTileCfgs] = {};
   LowpJob* ljobs = nullptr;
+  bool lvec = true;              // all FP32 jobs allow vectorised loads
   int njobs = 0;
   long long ntiles[kNumTileCfgs] = {};
   long long ltiles = 0;
@@ -133,7 +134,7 @@ hipError_t launch_mode_phase(const adr_batch& b, const ModePhase& m, hipStream_t
   if (b.precision == ADR_F64)
     return launch_mode_grouped_f64(m.cfg, m.kfast, m.jobs[(int)m.cfg], m.njobs,
                                    m.ntiles[(int)m.cfg], s);
-  return launch_tgemm_lowp_grouped(b.precision, m.ljobs, m.njobs, m.ltiles, s);
+  return launch_tgemm_lowp_grouped(b.precision, m.ljobs, m.njobs, m.ltiles, m.lvec, s);
 }
 
 // One ETD2RKds step of every problem of the plan (timed launch by launch when
@@ -390,6 +391,8 @@ int adr_batch_create(int count, const adr_problem* problems, double* const* U, d
             j.n_itiles = (g.n[mu] + 127) / 128;
             j.tile_begin = m.ltiles;
             m.ltiles += (long long)j.n_itiles * ((j.X + 127) / 128);
+            m.lvec = m.lvec && j.n % 4 == 0 && reinterpret_cast<uintptr_t>(j.W) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(j.M) % 16 == 0;
             lj[t][mu].push_back(j);
           }
         }

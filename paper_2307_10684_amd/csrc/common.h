@@ -78,8 +78,9 @@ struct LowpJob {
   int n_itiles;
   long long tile_begin;
 };
+// vec: every job has n % 4 == 0 and 16-byte aligned W and M (vectorised loads)
 hipError_t launch_tgemm_lowp_grouped(int precision, const LowpJob* jobs, int njobs,
-                                     long long ntiles, hipStream_t s);
+                                     long long ntiles, bool vec, hipStream_t s);
 // Split an FP64 n x n column-major matrix into transposed bf16 hi/lo parts.
 hipError_t launch_split_bf16(int n, const double* M, unsigned short* Mh, unsigned short* Ml,
                              hipStream_t s);

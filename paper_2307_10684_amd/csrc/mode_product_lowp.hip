@@ -118,17 +118,24 @@ __device__ __forceinline__ void tgemm_epilogue(const LowpJob& a, const f4 (&acc)
 // ------------------------------------------------------------------ FP32
 // Tile: BI rows i x BX fibres x, BK = 16 per chunk, four waves in a 2x2 grid.
 // The single-launch kernel and the grouped kernel (one LowpJob per product)
-// both call this.
-template <int BI, int BX, bool OUT64>
+// both call this.  VEC (n % 4 == 0, 16-byte aligned operands): every lane
+// moves four consecutive floats per load and per LDS store.
+template <int BI, int BX, bool OUT64, bool VEC>
 __device__ __forceinline__ void tgemm_f32_tile(const LowpJob& job, int itile, int xtile) {
   constexpr int BK = 16;
   constexpr int WI = 2, WX = 2;
   constexpr int TI = BI / WI, TX = BX / WX, FI = TI / 16, FX = TX / 16;
-  constexpr int LDI = BI + 32;   // [k][i] rows: next k-row 32 banks away
-  constexpr int LDK = BK + 1;    // [x][k] rows: odd pitch, conflict-free fragments
+  constexpr int LDI = BI + 32;            // [k][i] rows: next k-row 32 banks away
+  constexpr int LDK = VEC ? BK + 4 : BK + 1;  // [x][k] rows: 80 B (aligned, conflict-free) or odd pitch
+  // scalar mapping
   constexpr int MROWS = kThreads / BI, MLOADS = BK / MROWS;
   constexpr int XSTEP = kThreads / BK, WLOADS = BX / XSTEP;
   static_assert(MROWS * BI == kThreads && XSTEP * BK == kThreads, "mapping");
+  // vector mapping: M rows of BI/4 lanes, W fibres of BK/4 lanes
+  constexpr int MV = BI / 4, MVROWS = kThreads / MV, MVLOADS = BK / MVROWS;
+  constexpr int WV = BK / 4, WVSTEP = kThreads / WV, WVLOADS = BX / WVSTEP;
+  static_assert(MVROWS * MV == kThreads && MVLOADS * MVROWS == BK, "M vector mapping");
+  static_assert(WVSTEP * WV == kThreads && WVLOADS * WVSTEP == BX, "W vector mapping");
   __shared__ float sM[2][BK * LDI];
   __shared__ float sW[2][BX * LDK];
 
@@ -143,8 +150,27 @@ __device__ __forceinline__ void tgemm_f32_tile(const LowpJob& job, int itile, in
 
   const int m_i = tid % BI, m_k0 = tid / BI;
   const int w_k = tid % BK, w_x0 = tid / BK;
+  const int mv_i = 4 * (tid % MV), mv_k0 = tid / MV;
+  const int wv_k = 4 * (tid % WV), wv_x0 = tid / WV;
   float rm[MLOADS], rw[WLOADS];
+  f4 vm[MVLOADS], vw[WVLOADS];
   auto load = [&](int k0) {
+    if (VEC) {
+#pragma unroll
+      for (int p = 0; p < MVLOADS; ++p) {
+        const int i = i0 + mv_i, k = k0 + mv_k0 + p * MVROWS;
+        const bool ok = i < n && k < n;
+        vm[p] = *reinterpret_cast<const f4*>(M + (ok ? (unsigned)i + (unsigned)n * (unsigned)k : 0u));
+      }
+#pragma unroll
+      for (int p = 0; p < WVLOADS; ++p) {
+        const unsigned x = x0 + wv_x0 + p * WVSTEP;
+        const int k = k0 + wv_k;
+        const bool ok = x < X && k < n;
+        vw[p] = *reinterpret_cast<const f4*>(W + (ok ? x * (unsigned)n + (unsigned)k : 0u));
+      }
+      return;
+    }
 #pragma unroll
     for (int p = 0; p < MLOADS; ++p) {
       const int i = i0 + m_i, k = k0 + m_k0 + p * MROWS;
@@ -160,6 +186,20 @@ __device__ __forceinline__ void tgemm_f32_tile(const LowpJob& job, int itile, in
     }
   };
   auto store = [&](int buf, int k0) {
+    if (VEC) {
+      const f4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int p = 0; p < MVLOADS; ++p) {
+        const bool ok = (i0 + mv_i) < n && (k0 + mv_k0 + p * MVROWS) < n;
+        *reinterpret_cast<f4*>(&sM[buf][(mv_k0 + p * MVROWS) * LDI + mv_i]) = ok ? vm[p] : z;
+      }
+#pragma unroll
+      for (int p = 0; p < WVLOADS; ++p) {
+        const bool ok = (x0 + wv_x0 + p * WVSTEP) < X && (k0 + wv_k) < n;
+        *reinterpret_cast<f4*>(&sW[buf][(wv_x0 + p * WVSTEP) * LDK + wv_k]) = ok ? vw[p] : z;
+      }
+      return;
+    }
 #pragma unroll
     for (int p = 0; p < MLOADS; ++p) {
       const bool ok = (i0 + m_i) < n && (k0 + m_k0 + p * MROWS) < n;
@@ -206,7 +246,7 @@ __device__ __forceinline__ void tgemm_f32_tile(const LowpJob& job, int itile, in
   tgemm_epilogue<FI, FX, TI, TX, OUT64>(job, acc, i0 + wi * TI, x0 + wx * TX, col, krow);
 }
 
-template <int BI, int BX, bool OUT64>
+template <int BI, int BX, bool OUT64, bool VEC>
 __global__ __launch_bounds__(kThreads, 2) void k_tgemm_f32(LowpArgs a, int n_itiles,
                                                           int n_xtiles) {
   const int G = gridDim.x, b = blockIdx.x;
@@ -215,12 +255,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_tgemm_f32(LowpArgs a, int n_iti
   t /= n_itiles;
   const int xtile = t % n_xtiles;
   const int g = t / n_xtiles;
-  tgemm_f32_tile<BI, BX, OUT64>(job_of(a, g), itile, xtile);
+  tgemm_f32_tile<BI, BX, OUT64, VEC>(job_of(a, g), itile, xtile);
 }
 
 // Grouped FP32 products with FP32 outputs (one LowpJob per product, binary
 // search over the sorted tile offsets).
-template <int BI, int BX>
+template <int BI, int BX, bool VEC>
 __global__ __launch_bounds__(kThreads, 2) void k_tgemm_f32_grouped(const LowpJob* __restrict__ jobs,
                                                                   int njobs) {
   const long long t = blockIdx.x;
@@ -231,7 +271,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_tgemm_f32_grouped(const LowpJob
   }
   const LowpJob job = jobs[lo];
   const long long local = t - job.tile_begin;
-  tgemm_f32_tile<BI, BX, false>(job, (int)(local % job.n_itiles), (int)(local / job.n_itiles));
+  tgemm_f32_tile<BI, BX, false, VEC>(job, (int)(local % job.n_itiles), (int)(local / job.n_itiles));
 }
 
 // ------------------------------------------------------------------ split BF16
@@ -425,11 +465,23 @@ hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* co
   a.X = (unsigned)X;
   a.group = group;
   if (precision == 1) {
-    if (n <= 64)
-      return out_f64 ? launch_tiles(k_tgemm_f32<64, 128, true>, a, 64, 128, s)
-                     : launch_tiles(k_tgemm_f32<64, 128, false>, a, 64, 128, s);
-    return out_f64 ? launch_tiles(k_tgemm_f32<128, 128, true>, a, 128, 128, s)
-                   : launch_tiles(k_tgemm_f32<128, 128, false>, a, 128, 128, s);
+    // n % 4 == 0 with 16-byte aligned operands: four floats per lane per load
+    bool vec = n % 4 == 0;
+    for (int g = 0; g < group; ++g)
+      vec = vec && (reinterpret_cast<uintptr_t>(W[g]) % 16 == 0) &&
+            (reinterpret_cast<uintptr_t>(Mf32[g]) % 16 == 0);
+    if (n <= 64) {
+      if (vec)
+        return out_f64 ? launch_tiles(k_tgemm_f32<64, 128, true, true>, a, 64, 128, s)
+                       : launch_tiles(k_tgemm_f32<64, 128, false, true>, a, 64, 128, s);
+      return out_f64 ? launch_tiles(k_tgemm_f32<64, 128, true, false>, a, 64, 128, s)
+                     : launch_tiles(k_tgemm_f32<64, 128, false, false>, a, 64, 128, s);
+    }
+    if (vec)
+      return out_f64 ? launch_tiles(k_tgemm_f32<128, 128, true, true>, a, 128, 128, s)
+                     : launch_tiles(k_tgemm_f32<128, 128, false, true>, a, 128, 128, s);
+    return out_f64 ? launch_tiles(k_tgemm_f32<128, 128, true, false>, a, 128, 128, s)
+                   : launch_tiles(k_tgemm_f32<128, 128, false, false>, a, 128, 128, s);
   }
   // evenly tiled shapes with 16-byte aligned fibres take the vectorised loads
   bool aligned = true;
@@ -454,11 +506,15 @@ hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* co
 }
 
 hipError_t launch_tgemm_lowp_grouped(int precision, const LowpJob* jobs, int njobs,
-                                     long long ntiles, hipStream_t s) {
+                                     long long ntiles, bool vec, hipStream_t s) {
   if (precision != 1 || njobs <= 0 || ntiles <= 0 || ntiles > 0x7fffffffLL)
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_tgemm_f32_grouped<128, 128>), dim3((unsigned)ntiles), dim3(kThreads), 0, s,
-                     jobs, njobs);
+  if (vec)
+    hipLaunchKernelGGL((k_tgemm_f32_grouped<128, 128, true>), dim3((unsigned)ntiles),
+                       dim3(kThreads), 0, s, jobs, njobs);
+  else
+    hipLaunchKernelGGL((k_tgemm_f32_grouped<128, 128, false>), dim3((unsigned)ntiles),
+                       dim3(kThreads), 0, s, jobs, njobs);
   return hipGetLastError();
 }
 
