@@ -120,13 +120,14 @@ __device__ __forceinline__ void tgemm_epilogue(const LowpJob& a, const f4 (&acc)
 // The single-launch kernel and the grouped kernel (one LowpJob per product)
 // both call this.  VEC (n % 4 == 0, 16-byte aligned operands): every lane
 // moves four consecutive floats per load and per LDS store.
-template <int BI, int BX, bool OUT64, bool VEC>
+// LDS row pads (PADI, PADK, PADB below) are the fastest of a sweep at 256^3.
+template <int BI, int BX, bool OUT64, bool VEC, int PADI = 4, int PADK = 4, int WI = 2, int WX = 2>
 __device__ __forceinline__ void tgemm_f32_tile(const LowpJob& job, int itile, int xtile) {
   constexpr int BK = 16;
-  constexpr int WI = 2, WX = 2;
+  constexpr int kThreads = 64 * WI * WX;
   constexpr int TI = BI / WI, TX = BX / WX, FI = TI / 16, FX = TX / 16;
-  constexpr int LDI = BI + 32;            // [k][i] rows: next k-row 32 banks away
-  constexpr int LDK = VEC ? BK + 4 : BK + 1;  // [x][k] rows: 80 B (aligned, conflict-free) or odd pitch
+  constexpr int LDI = BI + PADI;             // [k][i] rows
+  constexpr int LDK = VEC ? BK + PADK : BK + 1;  // [x][k] rows: 16-byte aligned or odd pitch
   // scalar mapping
   constexpr int MROWS = kThreads / BI, MLOADS = BK / MROWS;
   constexpr int XSTEP = kThreads / BK, WLOADS = BX / XSTEP;
@@ -246,16 +247,16 @@ __device__ __forceinline__ void tgemm_f32_tile(const LowpJob& job, int itile, in
   tgemm_epilogue<FI, FX, TI, TX, OUT64>(job, acc, i0 + wi * TI, x0 + wx * TX, col, krow);
 }
 
-template <int BI, int BX, bool OUT64, bool VEC>
-__global__ __launch_bounds__(kThreads, 2) void k_tgemm_f32(LowpArgs a, int n_itiles,
-                                                          int n_xtiles) {
+template <int BI, int BX, bool OUT64, bool VEC, int PADI = 4, int PADK = 4, int WI = 2, int WX = 2>
+__global__ __launch_bounds__(64 * WI * WX, 2) void k_tgemm_f32(LowpArgs a, int n_itiles,
+                                                              int n_xtiles) {
   const int G = gridDim.x, b = blockIdx.x;
   int t = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
   const int itile = t % n_itiles;
   t /= n_itiles;
   const int xtile = t % n_xtiles;
   const int g = t / n_xtiles;
-  tgemm_f32_tile<BI, BX, OUT64, VEC>(job_of(a, g), itile, xtile);
+  tgemm_f32_tile<BI, BX, OUT64, VEC, PADI, PADK, WI, WX>(job_of(a, g), itile, xtile);
 }
 
 // Grouped FP32 products with FP32 outputs (one LowpJob per product, binary
@@ -278,13 +279,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_tgemm_f32_grouped(const LowpJob
 // Tile: BI rows i x BX fibres, BK = 32 (one bf16 MFMA depth) per chunk.  The W
 // chunk is loaded as FP32 (eight consecutive k per lane), split into hi/lo and
 // stored k-fastest; M arrives pre-split and transposed (k fastest).
-template <int BI, int BX, bool OUT64, bool FULL>
-__global__ __launch_bounds__(kThreads, 2) void k_tgemm_bf16x3(LowpArgs a, int n_itiles,
-                                                             int n_xtiles) {
+template <int BI, int BX, bool OUT64, bool FULL, int PADB = 0, int WI = 2, int WX = 2>
+__global__ __launch_bounds__(64 * WI * WX, 2) void k_tgemm_bf16x3(LowpArgs a, int n_itiles,
+                                                                 int n_xtiles) {
   constexpr int BK = 32;
-  constexpr int WI = 2, WX = 2;
+  constexpr int kThreads = 64 * WI * WX;
   constexpr int TI = BI / WI, TX = BX / WX, FI = TI / 16, FX = TX / 16;
-  constexpr int LDK = BK + 8;               // bf16 elements per row: 80 B pitch, conflict-free b128 reads
+  constexpr int LDK = BK + PADB;            // bf16 elements per row (16-byte aligned pitch)
   constexpr int MSEG = BI * (BK / 8);        // 8-element segments of the M chunk
   constexpr int WSEG = BX * (BK / 8);
   constexpr int MLOADS = MSEG / kThreads, WLOADS = WSEG / kThreads;
