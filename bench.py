@@ -219,7 +219,7 @@ def main(argv=None):
     ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16x3"])
     ap.add_argument("--scheme", default="etd2rkds", choices=["etd2rkds", "lawson2b"])
     ap.add_argument("--n", type=int, default=256, help="grid side of the 3D Brusselator workload")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true",

@@ -263,6 +263,9 @@ int adr_solve_monitored(const adr_problem* p, double* U, double* V, int nsteps, 
  */
 typedef struct adr_batch adr_batch;
 enum adr_batch_flags { ADR_BATCH_AUTOTUNE = 1, ADR_BATCH_GRAPH = 2, ADR_BATCH_PREPARED = 4 };
+/* ADR_BATCH_TILE(cfg): use tile configuration cfg (0..3, see adr_batch_info) for
+ * every FP64 mode-product phase instead of the default or the tuner's choice. */
+#define ADR_BATCH_TILE(cfg) (((cfg) + 1) << 8)
 int adr_batch_create(int count, const adr_problem* problems, double* const* U,
                      double* const* V, void* const* work, const size_t* work_bytes, int flags,
                      void* stream, adr_batch** plan);

@@ -30,6 +30,11 @@ ADR_SCHNAKENBERG, ADR_FHN, ADR_BRUSSELATOR, ADR_ZERO, ADR_DIB = 0, 1, 2, 3, 4
 ADR_MAX_PARAMS = 12
 ADR_BATCH_AUTOTUNE, ADR_BATCH_GRAPH, ADR_BATCH_PREPARED = 1, 2, 4
 
+
+def ADR_BATCH_TILE(cfg: int) -> int:
+    """Flag forcing tile configuration cfg (0..3) for the FP64 mode-product phases."""
+    return (int(cfg) + 1) << 8
+
 MODEL_IDS = {"schnakenberg": ADR_SCHNAKENBERG, "fhn": ADR_FHN,
              "brusselator": ADR_BRUSSELATOR, "zero": ADR_ZERO, "dib": ADR_DIB}
 SCHEME_IDS = {"etd2rkds": ADR_ETD2RKDS, "lawson2b": ADR_LAWSON2B}
@@ -457,6 +462,6 @@ class Batch:
             pass
 
 
-__all__ = [n for n in dir() if n.startswith(("adr_", "ADR_"))] + [
+__all__ = [n for n in dir() if n.startswith(("adr_", "ADR_"))] + ["ADR_BATCH_TILE"] + [
     "AdrProblem", "AdrError", "Solver", "Batch", "to_device_f64", "from_device", "EXPORTED",
     "LIB_PATH"]

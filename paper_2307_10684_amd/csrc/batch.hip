@@ -268,7 +268,10 @@ int adr_batch_create(int count, const adr_problem* problems, double* const* U, d
                      adr_batch** plan) {
   if (!plan) return ADR_EINVAL;
   *plan = nullptr;
-  if (flags & ~(ADR_BATCH_AUTOTUNE | ADR_BATCH_GRAPH | ADR_BATCH_PREPARED)) return ADR_EINVAL;
+  const int forced = (flags >> 8) & 0xff;   // 0: none, else tile configuration + 1
+  if ((flags & ~(ADR_BATCH_AUTOTUNE | ADR_BATCH_GRAPH | ADR_BATCH_PREPARED | (0xff << 8))) ||
+      forced > kNumTileCfgs)
+    return ADR_EINVAL;
   std::vector<Geometry> geoms;
   int st = validate(count, problems, U, V, work, work_bytes, geoms);
   if (st != ADR_OK) return st;
@@ -398,7 +401,7 @@ int adr_batch_create(int count, const adr_problem* problems, double* const* U, d
         }
       }
       m.njobs = lowp ? (int)lj[t][mu].size() : (int)tj[t][mu][0].size();
-      m.cfg = default_cfg(*b, mu);
+      m.cfg = forced ? (TileCfg)(forced - 1) : default_cfg(*b, mu);
     }
 
   // every buffer a launch will touch must exist
@@ -464,7 +467,7 @@ int adr_batch_create(int count, const adr_problem* problems, double* const* U, d
 
   // ---- autotune the tile shape of every FP64 mode phase (timed on phase 0's
   // buffers, whose outputs are workspace; phase 1 has the same shapes)
-  if ((flags & ADR_BATCH_AUTOTUNE) && !lowp) {
+  if ((flags & ADR_BATCH_AUTOTUNE) && !lowp && !forced) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     tune_cache_load();
     for (int mu = 0; mu < b->d_max; ++mu) {

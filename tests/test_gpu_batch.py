@@ -135,6 +135,18 @@ def test_batch_autotune(dev, mix_ref):
         assert np.array_equal(t[0], p[0]) and np.array_equal(t[1], p[1])
 
 
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3], ids=["64x64", "64x128", "128x64", "128x128"])
+def test_batch_every_tile_configuration(dev, mix_ref, cfg):
+    # each configuration of the grouped FP64 product gives the plan's default
+    # result bitwise (same summation order) and the oracle's within 1e-12
+    plain, _ = _run_batch(dev, MIX, mix_ref, STEPS, "f64", 0)
+    forced, info = _run_batch(dev, MIX, mix_ref, STEPS, "f64", dev.ADR_BATCH_TILE(cfg))
+    assert all(c == cfg for c in info[0][:3]), info
+    for w, f, p, r in zip(MIX, forced, plain, mix_ref):
+        assert np.array_equal(f[0], p[0]) and np.array_equal(f[1], p[1]), w.name
+        assert _err(f, (r[2], r[3])) <= TOL["f64"]
+
+
 def test_batch_rejects_unsupported(dev, mix_ref):
     w = MIX[0]
     U0, V0, _, _, mats = mix_ref[0]
