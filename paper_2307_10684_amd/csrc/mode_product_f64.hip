@@ -326,8 +326,7 @@ __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64_persist(ModeArg
   const int b = blockIdx.x;
   const int per = (ntiles + G - 1) / G;     // tiles per workgroup (upper bound)
   // workgroup b handles logical tiles base, base+1, ... within its XCD's range
-  const int xcd = b % 8, slot = b / 8, slots = (G + 7) / 8;
-  (void)slots;
+  const int xcd = b % 8, slot = b / 8;
 
   // per-tile state; the group member's pointers are picked with explicit selects
   // (a dynamic index into the kernel-argument arrays would spill them to scratch)
@@ -355,8 +354,24 @@ __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64_persist(ModeArg
     d.M = static_cast<const double*>(pick(a.M, d.g));
     return d;
   };
-  // logical tile k of this workgroup (k = 0, 1, ...); -1 when done
+  // logical tile k of this workgroup (k = 0, 1, ...); -1 when done.
+  // When the workgroups of an XCD can be grouped n_itiles at a time, the group
+  // members take the n_itiles row tiles of the same fibre blocks in lockstep:
+  // they read the same W chunks at about the same time, so the XCD's L2 serves
+  // the repeats and W is fetched from HBM about once.  (Measured at 256^3: a
+  // little faster for mu < d and 3-4 % slower for the last direction of a
+  // multi-dimensional tensor (R = 1), which keeps contiguous per-workgroup ranges.)
+  const int slots = G / 8;
+  const bool paired = (G % 8 == 0) && n_itiles > 1 && slots % n_itiles == 0 &&
+                      ntiles % n_itiles == 0 && (a.R > 1 || a.L == 1);
+  const int nu = ntiles / n_itiles;                        // fibre blocks (all tensors)
+  const int groups = 8 * (slots / n_itiles);
+  const int per_u = (nu + groups - 1) / groups;            // fibre blocks per group
   auto tile_index = [&](int k) {
+    if (paired) {
+      const int u = (xcd * (slots / n_itiles) + slot / n_itiles) * per_u + k;
+      return (k < per_u && u < nu) ? slot % n_itiles + n_itiles * u : -1;
+    }
     const int t = (G % 8 == 0) ? xcd * (G / 8) * per + slot * per + k : b * per + k;
     return (k < per && t < ntiles) ? t : -1;
   };
