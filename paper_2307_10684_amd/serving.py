@@ -338,14 +338,14 @@ class GpuBackend:
     on a copy stream into pinned host memory.  All streams have the default
     priority."""
 
-    def __init__(self, precision: str = "f64", device: str = "cuda"):
+    def __init__(self, precision: str = "f64", device: str = "cuda", graph: bool = False):
         import torch
-        from . import ADR_BATCH_PREPARED, PRECISION_IDS  # noqa: F401
         if precision not in ("f64", "f32"):
             raise ValueError("serving runs FP64 or FP32 products")
         self.torch = torch
         self.precision = precision
         self.device = device
+        self.graph = graph          # capture each plan's step in a HIP graph
         self.lanes = {}             # lane -> compute stream (created on first use)
         self.setup = torch.cuda.Stream(device)
         self.copy = torch.cuda.Stream(device)
@@ -384,8 +384,10 @@ class GpuBackend:
         return h
 
     def plan(self, handles):
-        from . import ADR_BATCH_PREPARED, adr_batch_create
+        from . import ADR_BATCH_GRAPH, ADR_BATCH_PREPARED, adr_batch_create
         flags = ADR_BATCH_PREPARED if self.precision == "f32" else 0
+        if self.graph:
+            flags |= ADR_BATCH_GRAPH
         return adr_batch_create([h.solver.problem for h in handles], [h.U for h in handles],
                                 [h.V for h in handles], [h.solver.work for h in handles], flags,
                                 self.setup)
