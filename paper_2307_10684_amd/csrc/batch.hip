@@ -114,9 +114,10 @@ struct adr_batch {
   std::vector<Carve> carves;
   std::vector<double*> U, V;
   char* dev = nullptr;           // all device job tables
-  StageJob* stage1 = nullptr;
+  StageJob* stage1 = nullptr;    // point-kernel jobs first, then tiled-kernel jobs
   int n_stage = 0;
-  long long stage1_blocks = 0;
+  int n_stage1[2] = {0, 0};       // jobs per stage-1 variant (point, tile)
+  long long stage1_blocks[2] = {0, 0};
   PointJob* stage2 = nullptr;
   PointJob* finalize = nullptr;  // reduced precision only
   long long point_blocks = 0;
@@ -142,9 +143,15 @@ hipError_t launch_mode_phase(const adr_batch& b, const ModePhase& m, hipStream_t
 hipError_t batch_step(const adr_batch& b, hipStream_t s, bool capturing) {
   const bool lowp = b.precision != ADR_F64;
   auto run = [&](int kind, auto&& f) { return capturing ? f() : timed(kind, s, f); };
-  hipError_t e = run(kKindStage, [&] {
-    return launch_stage1_grouped(b.stage1, b.n_stage, b.stage1_blocks, lowp ? 1 : 0, s);
-  });
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    if (b.n_stage1[k] == 0) continue;
+    const StageJob* jobs = b.stage1 + (k == 0 ? 0 : b.n_stage1[0]);
+    const int kind = k == 0 ? kStage1Point : kStage1Tile;
+    e = run(kKindStage, [&] {
+      return launch_stage1_grouped(jobs, b.n_stage1[k], b.stage1_blocks[k], kind, lowp ? 1 : 0, s);
+    });
+  }
   for (int mu = 0; mu < b.d_max && e == hipSuccess; ++mu)
     e = run(kKindMode, [&] { return launch_mode_phase(b, b.mode[0][mu], s); });
   if (e == hipSuccess)
@@ -292,7 +299,7 @@ int adr_batch_create(int count, const adr_problem* problems, double* const* U, d
   // ---- host job tables
   std::vector<StageJob> s1(count);
   std::vector<PointJob> s2(count), fin(count);
-  long long blocks = 0, pblocks = 0;
+  long long pblocks = 0;
   for (int i = 0; i < count; ++i) {
     const adr_problem* p = &b->probs[i];
     const Geometry& g = geoms[i];
@@ -309,8 +316,7 @@ int adr_batch_create(int count, const adr_problem* problems, double* const* U, d
     j.R[1] = b->carves[i].R[1];
     int gz;
     const int nb = stage1_plan(j.g, j.kind, j.gx, j.gy, gz);
-    j.block_begin = blocks;
-    blocks += nb;
+    j.block_begin = nb;   // block count for now; offsets once the jobs are ordered
     PointJob& q = s2[i];
     q = PointJob{};
     q.kind = lowp ? 1 : 0;
@@ -337,8 +343,17 @@ int adr_batch_create(int count, const adr_problem* problems, double* const* U, d
     pblocks += (g.N + 255) / 256;
   }
   b->n_stage = count;
-  b->stage1_blocks = blocks;
   b->point_blocks = pblocks;
+  // stage-1 table: point-kernel jobs, then tiled-kernel jobs, offsets per segment
+  std::stable_sort(s1.begin(), s1.end(),
+                   [](const StageJob& x, const StageJob& y) { return x.kind < y.kind; });
+  for (StageJob& j : s1) {
+    const int k = j.kind == kStage1Tile ? 1 : 0;
+    const long long nb = j.block_begin;
+    j.block_begin = b->stage1_blocks[k];
+    b->stage1_blocks[k] += nb;
+    ++b->n_stage1[k];
+  }
 
   // mode phases: for Tucker t and direction mu, two jobs (u, v) per problem with d > mu
   std::vector<TileJob> tj[2][kMaxMu][kNumTileCfgs];
@@ -398,6 +413,29 @@ int adr_batch_create(int count, const adr_problem* problems, double* const* U, d
                      reinterpret_cast<uintptr_t>(j.M) % 16 == 0;
             lj[t][mu].push_back(j);
           }
+        }
+      }
+      // largest contractions first (work per tile grows with n): the long tiles
+      // start early and the short ones fill the end of the launch.  Each tile's
+      // arithmetic does not depend on its position, so results are unchanged.
+      for (int k = 0; k < kNumTileCfgs; ++k) {
+        auto& v = tj[t][mu][k];
+        std::stable_sort(v.begin(), v.end(), [](const TileJob& x, const TileJob& y) { return x.n > y.n; });
+        long long off = 0;
+        for (TileJob& j : v) {
+          int BI, BX;
+          tile_cfg_dims((TileCfg)k, BI, BX);
+          j.tile_begin = off;
+          off += (long long)j.n_itiles * ((j.X + BX - 1) / BX);
+        }
+      }
+      {
+        auto& v = lj[t][mu];
+        std::stable_sort(v.begin(), v.end(), [](const LowpJob& x, const LowpJob& y) { return x.n > y.n; });
+        long long off = 0;
+        for (LowpJob& j : v) {
+          j.tile_begin = off;
+          off += (long long)j.n_itiles * ((j.X + 127) / 128);
         }
       }
       m.njobs = lowp ? (int)lj[t][mu].size() : (int)tj[t][mu][0].size();

@@ -123,8 +123,9 @@ struct PointJob {
   void* R[2];              // kinds 0, 1: outputs
   long long block_begin;
 };
-hipError_t launch_stage1_grouped(const StageJob* jobs, int njobs, long long nblocks, int r_f32,
-                                 hipStream_t s);
+// all jobs of one launch use the variant `kind` (kStage1Point or kStage1Tile)
+hipError_t launch_stage1_grouped(const StageJob* jobs, int njobs, long long nblocks, int kind,
+                                 int r_f32, hipStream_t s);
 hipError_t launch_pointwise_grouped(const PointJob* jobs, int njobs, long long nblocks, int r_f32,
                                     hipStream_t s);
 // Stage-1 variant and block grid of one problem (gx * gy * gz blocks of 64 x 4).
@@ -153,6 +154,20 @@ hipError_t launch_lawson_stage1(long long N, const Reaction& r, double tau, cons
 // Lawson2b stage 2: C += tau/2 G^c(U2, V2)  (C holds the second Tucker result).
 hipError_t launch_lawson_stage2(long long N, const Reaction& r, double tau, double* U, double* V,
                                 const double* U2, const double* V2, hipStream_t s);
+
+// Logical tile of workgroup b in a launch of G workgroups.  Workgroups are
+// dealt to the 8 XCDs round-robin and each XCD has its own L2.  Logical tiles
+// are taken in chunks of C consecutive tiles, and the chunks are dealt to the
+// XCDs round-robin: the tiles of a chunk (e.g. the row tiles of one fibre
+// block, which read the same operand data) run on one XCD at about the same
+// time and share its L2, while every XCD gets a similar mix of large and small
+// jobs.  Workgroups beyond the last whole round of 8 C keep their index.
+__device__ __forceinline__ long long xcd_tile(long long b, long long G, long long C = 8) {
+  const long long span = 8 * C, Gs = (G / span) * span;
+  if (b >= Gs) return b;
+  const long long k = b % 8, j = b / 8;
+  return ((j / C) * 8 + k) * C + (j % C);
+}
 
 // Dynamics indicators (trapezoidal means, increment norms, non-finite count)
 // into rec[0..4]; `partial` holds 5 * indicator_blocks(N) doubles.  Up and Vp

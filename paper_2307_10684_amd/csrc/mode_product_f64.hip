@@ -264,7 +264,7 @@ __global__ __launch_bounds__(64 * WI * WX, 2) void k_mode_f64_grouped(const Tile
   constexpr int SW = KFAST ? BX * (BK + 2) : BK * (BX + kPad);
   __shared__ double sM[2 * BK * (BI + kPad)];
   __shared__ double sW[2 * SW];
-  const long long t = blockIdx.x;
+  const long long t = xcd_tile(blockIdx.x, gridDim.x);
   int lo = 0, hi = njobs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;

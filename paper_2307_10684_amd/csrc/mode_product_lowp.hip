@@ -264,7 +264,7 @@ __global__ __launch_bounds__(64 * WI * WX, 2) void k_tgemm_f32(LowpArgs a, int n
 template <int BI, int BX, bool VEC>
 __global__ __launch_bounds__(kThreads, 2) void k_tgemm_f32_grouped(const LowpJob* __restrict__ jobs,
                                                                   int njobs) {
-  const long long t = blockIdx.x;
+  const long long t = xcd_tile(blockIdx.x, gridDim.x);
   int lo = 0, hi = njobs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;

@@ -315,11 +315,13 @@ __global__ __launch_bounds__(256) void k_etd_stage1_tile(StageGeom g, Reaction r
   etd_stage1_tile<TR, ZB>(g, r, U, V, Ru, Rv, bx, by, bz);
 }
 
-// Grouped stage 1 over several problems: job j owns blocks
-// [jobs[j].block_begin, jobs[j+1].block_begin), laid out as gx * gy * gz, and
-// runs the kernel variant its own size selects (kind), so a problem computes
-// the same values alone and in any mix.
-template <typename TR>
+// Grouped stage 1 over several problems of one kernel variant (KIND): job j
+// owns blocks [jobs[j].block_begin, jobs[j+1].block_begin), laid out as
+// gx * gy * gz.  The variant follows from each problem's own size
+// (stage1_plan), so a problem computes the same values alone and in any mix;
+// the two variants are separate launches so that the small-grid kernel keeps
+// its small register footprint (and occupancy).
+template <typename TR, int KIND>
 __global__ __launch_bounds__(256) void k_etd_stage1_grouped(const StageJob* __restrict__ jobs,
                                                             int njobs) {
   const long long b = blockIdx.x;
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(256) void k_etd_stage1_grouped(const StageJob* __re
   const StageJob& j = jobs[lo];
   const int local = (int)(b - j.block_begin);
   const int bx = local % j.gx, rest = local / j.gx;
-  if (j.kind == kStage1Tile)
+  if (KIND == kStage1Tile)
     etd_stage1_tile<TR, kZB>(j.g, j.r, j.U, j.V, j.R[0], j.R[1], bx, rest % j.gy, rest / j.gy);
   else
     etd_stage1_point<TR>(j.g, j.r, j.U, j.V, j.R[0], j.R[1], bx, rest % j.gy, rest / j.gy);
@@ -560,14 +562,21 @@ hipError_t launch_lawson_stage2(long long N, const Reaction& r, double tau, doub
   return hipGetLastError();
 }
 
-hipError_t launch_stage1_grouped(const StageJob* jobs, int njobs, long long nblocks, int r_f32,
-                                 hipStream_t s) {
+hipError_t launch_stage1_grouped(const StageJob* jobs, int njobs, long long nblocks, int kind,
+                                 int r_f32, hipStream_t s) {
   if (njobs <= 0 || nblocks <= 0 || nblocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  const dim3 block(64, 4);
-  if (r_f32)
-    hipLaunchKernelGGL(k_etd_stage1_grouped<float>, dim3((unsigned)nblocks), block, 0, s, jobs, njobs);
-  else
-    hipLaunchKernelGGL(k_etd_stage1_grouped<double>, dim3((unsigned)nblocks), block, 0, s, jobs, njobs);
+  const dim3 block(64, 4), grid((unsigned)nblocks);
+  if (kind == kStage1Tile) {
+    if (r_f32)
+      hipLaunchKernelGGL((k_etd_stage1_grouped<float, kStage1Tile>), grid, block, 0, s, jobs, njobs);
+    else
+      hipLaunchKernelGGL((k_etd_stage1_grouped<double, kStage1Tile>), grid, block, 0, s, jobs, njobs);
+  } else {
+    if (r_f32)
+      hipLaunchKernelGGL((k_etd_stage1_grouped<float, kStage1Point>), grid, block, 0, s, jobs, njobs);
+    else
+      hipLaunchKernelGGL((k_etd_stage1_grouped<double, kStage1Point>), grid, block, 0, s, jobs, njobs);
+  }
   return hipGetLastError();
 }
 
