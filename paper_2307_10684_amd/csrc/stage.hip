@@ -489,7 +489,10 @@ unsigned stream_grid(long long N) {
 
 int stage1_plan(const StageGeom& g, int& kind, int& gx, int& gy, int& gz) {
   const int n2 = g.d >= 2 ? g.n[1] : 1, n3 = g.d >= 3 ? g.n[2] : 1;
-  kind = (g.N >= (1LL << 20) && g.d >= 2) ? kStage1Tile : kStage1Point;
+  // measured crossovers: the LDS-tiled kernel wins from 2^20 points in 3D and
+  // from 2^16 in 2D; below, the one-plane kernel's independent loads win
+  kind = ((g.d == 3 && g.N >= (1LL << 20)) || (g.d == 2 && g.N >= (1LL << 16))) ? kStage1Tile
+                                                                               : kStage1Point;
   gx = (g.n[0] + 63) / 64;
   gy = kind == kStage1Tile ? (n2 + kTY - 1) / kTY : (n2 + 3) / 4;
   gz = kind == kStage1Tile ? (n3 + kZB - 1) / kZB : n3;
