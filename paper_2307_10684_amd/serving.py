@@ -54,6 +54,9 @@ class Job:
     workload: Any
     steps: int
     initial: Callable[[], tuple]
+    # polled between rounds: once it returns True the request is dropped
+    # (queued or running) and completes with status "cancelled"
+    cancelled: Optional[Callable[[], bool]] = None
 
     @property
     def N(self) -> int:
@@ -68,8 +71,10 @@ class Completion:
     finished: float
     steps: int
     grid_points: int
-    status: str = "ok"              # "ok" or "rejected" (larger than the whole budget)
+    status: str = "ok"              # "ok", "rejected" (larger than the whole budget),
+                                    # "failed" (set-up raised), "cancelled"
     result: Optional[tuple] = None
+    error: Optional[str] = None
 
     @property
     def latency(self) -> float:
@@ -181,19 +186,33 @@ class Engine:
             if plans[pid][1] == 0:
                 be.release_plan(plans.pop(pid)[0])
 
-        def finish(s: _Slot, t: float, result=None):
+        def finish(s: _Slot, t: float, result=None, status="ok"):
             nonlocal used
             done.append(Completion(s.job.rid, s.job.arrival, s.admitted, t, s.job.steps,
-                                   s.job.N, "ok", result))
+                                   s.job.N, status, result))
             used -= s.bytes
             slots.remove(s)
             lane_of_slot.pop(s.serial, None)
             be.release(s.handle)
 
+        def is_cancelled(job: Job) -> bool:
+            return job.cancelled is not None and bool(job.cancelled())
+
+        def in_flight(s: _Slot) -> bool:
+            return any(s in r.members for ln in lanes for r in ln.inflight)
+
         while True:
             t = now()
             while pending and pending[0].arrival <= t:
                 queue.append(pending.popleft())
+            # cancellations: queued requests leave at once; admitted ones once no
+            # round that includes them is in flight
+            for job in [j for j in queue if is_cancelled(j)]:
+                queue.remove(job)
+                done.append(Completion(job.rid, job.arrival, now(), now(), job.steps, job.N,
+                                       "cancelled"))
+            for sl in [x for x in slots if is_cancelled(x.job) and not in_flight(x)]:
+                finish(sl, now(), None, "cancelled")
             # admission: first come, first served, while slots and budget allow
             while queue and len(slots) < self.max_active:
                 job = queue[0]
@@ -206,7 +225,12 @@ class Engine:
                 if used + need > self.budget:
                     break
                 queue.popleft()
-                handle = be.admit(job)
+                try:
+                    handle = be.admit(job)
+                except Exception as exc:   # a request that cannot be set up fails alone
+                    done.append(Completion(job.rid, job.arrival, now(), now(), job.steps, job.N,
+                                           "failed", error=f"{type(exc).__name__}: {exc}"))
+                    continue
                 used += need
                 serial += 1
                 s = _Slot(serial, job, handle, need, now(), job.steps)
@@ -236,7 +260,8 @@ class Engine:
                     progressed = True
             # new rounds
             for ln in lanes:
-                runnable = [s for s in slots if s.left > 0 and lane_of_slot[s.serial] == ln.index]
+                runnable = [s for s in slots if s.left > 0 and lane_of_slot[s.serial] == ln.index
+                            and not is_cancelled(s.job)]
                 if not runnable:
                     if ln.plan_id is not None:
                         drop_plan(ln.plan_id)
@@ -280,7 +305,10 @@ class Engine:
         lat = np.array([c.latency for c in ok]) if ok else np.zeros(1)
         gps = sum(c.steps * c.grid_points for c in ok)
         self.stats = {
-            "requests": len(done), "rejected": len(done) - len(ok),
+            "requests": len(done),
+            "rejected": sum(1 for c in done if c.status == "rejected"),
+            "failed": sum(1 for c in done if c.status == "failed"),
+            "cancelled": sum(1 for c in done if c.status == "cancelled"),
             "makespan_s": end, "grid_point_steps": gps,
             "throughput": gps / end if end > 0 else 0.0,
             "p50_latency_s": float(np.percentile(lat, 50)),

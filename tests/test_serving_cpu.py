@@ -275,3 +275,62 @@ def test_sequential_path_matches_and_batching_lowers_latency():
     # the model device is serial, so batching cannot be faster in total, but the
     # short requests no longer wait behind long ones
     assert eng.stats["p50_latency_s"] <= seq_stats["p50_latency_s"] * 1.5
+
+
+class FailingBackend(FakeBackend):
+    """Set-up of the listed requests raises (as a device allocation might)."""
+
+    def __init__(self, clock, fail_rids, **kw):
+        super().__init__(clock, **kw)
+        self.fail_rids = set(fail_rids)
+
+    def admit(self, job):
+        if job.rid in self.fail_rids:
+            raise MemoryError(f"no device memory for request {job.rid}")
+        return super().admit(job)
+
+
+def test_a_failed_setup_fails_alone():
+    clock = Clock()
+    be = FailingBackend(clock, fail_rids={2, 5})
+    jobs = _jobs(8, seed=8)
+    done = {c.rid: c for c in _engine(clock, be, max_chunk=3).run(jobs)}
+    assert done[2].status == "failed" and "MemoryError" in done[2].error
+    assert done[5].status == "failed"
+    for j in jobs:
+        if j.rid in (2, 5):
+            continue
+        U, V = _alone(j)
+        assert done[j.rid].status == "ok"
+        assert np.array_equal(done[j.rid].result[0], U) and np.array_equal(done[j.rid].result[1], V)
+    assert be.live == 0 and be.mem == 0 and be.plans_alive == 0
+
+
+def test_cancellation_of_running_and_queued_requests():
+    clock = Clock()
+    be = FakeBackend(clock, cost=1e-5)
+    jobs = _jobs(6, seed=9, spacing=1e-4, steps=(20, 30))
+    t_cut = 0.004
+    # a running request cancelled mid-run, and one cancelled while still queued
+    jobs[1].cancelled = lambda: clock.t > t_cut
+    late = S.with_shape(S.schnakenberg_2d(), (9, 9))
+    jobs.append(serving.Job(50, 0.01, late, 5, lambda: S.initial_state(late, 1),
+                            cancelled=lambda: True))
+    eng = _engine(clock, be, max_chunk=2)
+    done = {c.rid: c for c in eng.run(jobs)}
+    assert done[1].status == "cancelled" and done[1].result is None
+    assert done[50].status == "cancelled"
+    assert eng.stats["cancelled"] == 2
+    steps_run = {}
+    for members, steps, _ in be.rounds:
+        for r in members:
+            steps_run[r] = steps_run.get(r, 0) + steps
+    assert 0 < steps_run.get(1, 0) < jobs[1].steps      # it ran, then stopped
+    assert 50 not in steps_run                          # never admitted to a round
+    for j in jobs:
+        if j.rid in (1, 50):
+            continue
+        U, V = _alone(j)
+        assert done[j.rid].status == "ok"
+        assert np.array_equal(done[j.rid].result[0], U) and np.array_equal(done[j.rid].result[1], V)
+    assert be.live == 0 and be.mem == 0 and be.plans_alive == 0
