@@ -2,7 +2,8 @@
 """Benchmark of the ETD2RKds hot path on one MI355X.
 
 One "step" is one ETD2RKds step (Sec. 3, eq. (11)) of both components over
-the whole grid: two stage kernels and 2*d grouped mu-mode-product launches.
+the whole grid: the stage-1 kernel, 2*d grouped mu-mode-product launches and,
+where the last product of the phi_1 operator cannot carry it, a stage-2 kernel.
 Default workload: the 3D advective Brusselator on a 256^3 grid (tau = 5e-3,
 FP64), with seeded synthetic initial data already resident in HBM.
 
@@ -68,9 +69,10 @@ def _traffic_from_profiles(precision: str, workload: str):
         return None
 
 
-def _stage_traffic_from_profiles(workload: str):
-    """Average HBM bytes per launch of the two FP64 stage kernels from the committed
-    counter summary, or None (no summary, or stage.hip changed since)."""
+def _stage_traffic_from_profiles(workload: str, stage1_only: bool):
+    """Average HBM bytes per launch of the FP64 stage kernels of a step (stage 1
+    alone when the mode product carries stage 2) from the committed counter
+    summary, or None (no summary, or stage.hip changed since)."""
     path = os.path.join(ROOT, "profiles", f"stage_kernels_{workload}_counters.txt")
     if not os.path.exists(path):
         return None
@@ -82,8 +84,10 @@ def _stage_traffic_from_profiles(workload: str):
     if vals.get("kernel_source_sha256_16") != _src_hash("stage.hip"):
         return None
     try:
-        return 0.5 * (float(vals["k_etd_stage1_tile_hbm_bytes_per_launch"]) +
-                      float(vals["k_etd_stage2_hbm_bytes_per_launch"]))
+        s1 = float(vals["k_etd_stage1_tile_hbm_bytes_per_launch"])
+        if stage1_only:
+            return s1
+        return 0.5 * (s1 + float(vals["k_etd_stage2_hbm_bytes_per_launch"]))
     except (KeyError, ValueError):
         return None
 
@@ -321,16 +325,24 @@ def main(argv=None):
             "bf16x3": PEAKS["bf16_mfma_tflops"]}[args.precision]
     achieved = flops_per_launch / (mode_avg_ms * 1e-3) / 1e12
     bytes_per_launch = 2 * 2 * elem * N  # read + write one tensor per component
+    if args.precision == "f64" and args.scheme == "etd2rkds" and n_stage < 1.5 * args.steps:
+        # one product per step also carries stage 2 (48 B/point), averaged over the 2d launches
+        bytes_per_launch += 48 * N / (2 * d)
     # split BF16: three products' MFMA time (3 x flops at 2.5 PFLOP/s) is below the
     # time to move its FP32 operands, so its roofline is HBM
     hbm_bound = args.precision == "bf16x3"
     traffic = _traffic_from_profiles(args.precision, w.name)
     stage_avg_ms = ms_stage / max(n_stage, 1)
     # algorithmic bytes per point of the stage kernels, averaged over the launches of a step:
-    # FP64: stage 1 (read U,V; write R1u,R1v) 32 B, stage 2 (read U,V,U2,V2; write R2) 48 B;
+    # FP64: stage 1 (read U,V; write R1u,R1v) 32 B, and stage 2 (read U,V,U2,V2; write R2)
+    # 48 B unless the last product of the phi_1 operator carries it (then stage 1 only);
     # reduced precision: stage 1 24 B (FP32 R1), stage 2 32 B (FP32 D1 in, R2 out),
     # final C += D1 + D2 48 B
-    stage_bytes = ((32 + 48) / 2 if args.precision == "f64" else (24 + 32 + 48) / 3) * N
+    stage_per_step = n_stage / max(args.steps, 1)
+    if args.precision == "f64":
+        stage_bytes = (32.0 if stage_per_step < 1.5 else (32 + 48) / 2) * N
+    else:
+        stage_bytes = (24 + 32 + 48) / 3 * N
 
     line = {
         "metric": METRIC,
@@ -372,7 +384,7 @@ def main(argv=None):
             "frac": stage_bytes / (stage_avg_ms * 1e-3) / 1e9 / PEAKS["hbm_gbs"],
             "launches": n_stage,
             "algorithmic_bytes_per_launch": stage_bytes,
-            "traffic": (_stage_traffic_from_profiles(w.name)
+            "traffic": (_stage_traffic_from_profiles(w.name, stage_per_step < 1.5)
                         if args.precision == "f64" and args.scheme == "etd2rkds" else None),
         },
         "timing_pass_ms_per_step": 1e3 * elapsed_ev / args.steps,

@@ -42,34 +42,59 @@ struct TuckerGroup {
 // reduced precisions chain transposing products (each reads contiguous fibres
 // and writes the next direction's fibres contiguous); their intermediates are
 // FP32 and the last product writes the FP64 result in the natural layout.
+// Optional ETD2RKds stage 2 carried by the last FP64 product (see ModeArgs::Rout).
+struct Stage2Fuse {
+  void* R[2];
+  Reaction r;
+};
+
+// The FP64 mode-product arguments of direction mu of run_tucker's chain.
+ModeArgs tucker_mode_args(const Geometry& g, const TuckerGroup& tg, int mu, const void* const* W,
+                          void* const* out, double alpha, double beta) {
+  const bool last = (mu == g.d - 1);
+  ModeArgs a{};
+  for (int k = 0; k < tg.count; ++k) {
+    a.W[k] = W[k];
+    a.out[k] = out[k];
+    a.M[k] = tg.M[k][mu];
+    a.Y[k] = last ? tg.Y[k] : nullptr;
+    a.Z[k] = nullptr;
+  }
+  a.alpha = last ? alpha : 1.0;
+  a.beta = last ? beta : 0.0;
+  a.gamma = 0.0;
+  mode_geometry(g, mu, a.L, a.R);
+  a.X = a.L * a.R;
+  a.n = g.n[mu];
+  a.group = tg.count;
+  return a;
+}
+
+// The tensor that direction mu of run_tucker's chain reads (mu > 0: a ping-pong buffer).
+const void* tucker_input(const TuckerGroup& tg, int k, int mu) {
+  return (mu == 0) ? tg.in[k] : ((mu % 2 == 1) ? tg.t1[k] : tg.t2[k]);
+}
+
 hipError_t run_tucker(const Geometry& g, const TuckerGroup& tg, double alpha, double beta,
-                      int precision, hipStream_t s, bool last_f32 = false) {
+                      int precision, hipStream_t s, bool last_f32 = false,
+                      const Stage2Fuse* fuse = nullptr) {
   for (int mu = 0; mu < g.d; ++mu) {
     const bool last = (mu == g.d - 1);
     const void* W[kMaxGroup];
     void* out[kMaxGroup];
     for (int k = 0; k < tg.count; ++k) {
-      W[k] = (mu == 0) ? tg.in[k] : ((mu % 2 == 1) ? tg.t1[k] : tg.t2[k]);
+      W[k] = tucker_input(tg, k, mu);
       out[k] = last ? tg.out[k] : ((mu % 2 == 0) ? tg.t1[k] : tg.t2[k]);
       if (!W[k] || !out[k] || W[k] == out[k]) return hipErrorInvalidValue;
     }
     hipError_t e;
     if (precision == ADR_F64) {
-      ModeArgs a{};
-      for (int k = 0; k < tg.count; ++k) {
-        a.W[k] = W[k];
-        a.out[k] = out[k];
-        a.M[k] = tg.M[k][mu];
-        a.Y[k] = last ? tg.Y[k] : nullptr;
-        a.Z[k] = nullptr;
+      ModeArgs a = tucker_mode_args(g, tg, mu, W, out, alpha, beta);
+      if (last && fuse) {
+        a.Rout[0] = fuse->R[0];
+        a.Rout[1] = fuse->R[1];
+        a.react = fuse->r;
       }
-      a.alpha = last ? alpha : 1.0;
-      a.beta = last ? beta : 0.0;
-      a.gamma = 0.0;
-      mode_geometry(g, mu, a.L, a.R);
-      a.X = a.L * a.R;
-      a.n = g.n[mu];
-      a.group = tg.count;
       e = timed(kKindMode, s, [&] { return launch_mode_product_f64(a, s); });
     } else {
       const void* Mf[kMaxGroup];
@@ -300,13 +325,39 @@ hipError_t step_etd2rkds(const adr_problem* p, const Geometry& g, const Carve& c
   tg.out[1] = c.V2;
   tg.Y[0] = U;
   tg.Y[1] = V;
-  e = run_tucker(g, tg, p->tau, 1.0, p->precision, s);
+  // stage 2: R^c = G^c(U_{n2}, V_{n2}) - G^c(U_n, V_n), in the epilogue of the
+  // last product when its shape allows (the product then writes R^c into the
+  // buffer it does not read: R when d = 2, T when d = 3), else as its own pass
+  const int last = g.d - 1;
+  Stage2Fuse fuse{};
+  bool fused = false;
+  if (g.d >= 2) {
+    const void* W[kMaxGroup];
+    void* out[kMaxGroup];
+    for (int cc = 0; cc < 2; ++cc) {
+      W[cc] = tucker_input(tg, cc, last);
+      out[cc] = tg.out[cc];
+      fuse.R[cc] = (W[cc] == c.R[cc]) ? c.T[cc] : c.R[cc];
+    }
+    fuse.r = r;
+    fused = mode_f64_stage2_fusable(tucker_mode_args(g, tg, last, W, out, p->tau, 1.0)) &&
+            fuse.R[0] != W[0] && fuse.R[1] != W[1];
+  }
+  e = run_tucker(g, tg, p->tau, 1.0, p->precision, s, false, fused ? &fuse : nullptr);
   if (e != hipSuccess) return e;
-  // stage 2: R^c = G^c(U_{n2}, V_{n2}) - G^c(U_n, V_n)
-  e = timed(kKindStage, s, [&] {
-    return launch_etd_stage2(g.N, r, U, V, c.U2, c.V2, c.R[0], c.R[1], lowp ? 1 : 0, s);
-  });
-  if (e != hipSuccess) return e;
+  if (fused) {
+    // phi_2 chain from the buffer stage 2 wrote; the other one is its first ping buffer
+    for (int cc = 0; cc < 2; ++cc) {
+      tg.in[cc] = fuse.R[cc];
+      tg.t1[cc] = (fuse.R[cc] == c.R[cc]) ? c.T[cc] : c.R[cc];
+      tg.t2[cc] = fuse.R[cc];
+    }
+  } else {
+    e = timed(kKindStage, s, [&] {
+      return launch_etd_stage2(g.N, r, U, V, c.U2, c.V2, c.R[0], c.R[1], lowp ? 1 : 0, s);
+    });
+    if (e != hipSuccess) return e;
+  }
   // C_{n+1} = C_{n2} + 2^(d-1) tau * Tucker(R^c; phi_2)
   for (int cc = 0; cc < 2; ++cc)
     for (int mu = 0; mu < g.d; ++mu) set_phi(tg, cc, p, c, cc, 2, mu);

@@ -15,6 +15,13 @@ constexpr int kMaxGroup = 4;
 
 enum class Elem : int { F64 = 0, F32 = 1 };
 
+// Reaction model constants as passed to the stage kernels and
+// to the FP64 mode product when it carries ETD2RKds stage 2.
+struct Reaction {
+  int model;
+  double p[12];
+};
+
 // Geometry of one mu-mode product on an order-d tensor stored first index
 // fastest: the tensor is viewed as (L, n, R) with L = prod_{nu<mu} n_nu,
 // R = prod_{nu>mu} n_nu.  A fibre index x in [0, L*R) stands for (l, r) with
@@ -29,7 +36,15 @@ struct ModeArgs {
   long long L, R, X;             // X = L*R fibres
   int n;                         // n_mu (fibre length, matrix size)
   int group;                     // number of tensors in the launch (1..kMaxGroup)
+  // ETD2RKds stage 2 carried by the last product of the phi_1 Tucker operator
+  // (group = 2: U then V, Y = the states C_n, out = C_{n2}):
+  //   Rout[c] = G^c(out[0], out[1]) - G^c(Y[0], Y[1]); null when not fused.
+  void* Rout[2];
+  Reaction react;
 };
+// Whether launch_mode_product_f64 can carry stage 2 for this product (a.Rout
+// set): an evenly tiled x-contiguous product of two tensors with addends.
+bool mode_f64_stage2_fusable(const ModeArgs& a);
 
 // One product of a grouped launch (also the per-tile view of a single product).
 struct TileJob {
@@ -84,12 +99,6 @@ hipError_t launch_tgemm_lowp_grouped(int precision, const LowpJob* jobs, int njo
 // Split an FP64 n x n column-major matrix into transposed bf16 hi/lo parts.
 hipError_t launch_split_bf16(int n, const double* M, unsigned short* Mh, unsigned short* Ml,
                              hipStream_t s);
-
-// Reaction model constants as passed to the stage kernels.
-struct Reaction {
-  int model;
-  double p[12];
-};
 
 struct StageGeom {
   int d;

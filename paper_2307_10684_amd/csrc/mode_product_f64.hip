@@ -24,6 +24,7 @@
 // Element indices fit in 32 bits (the host rejects tensors of 2^31 or more
 // elements), so loads use a 32-bit offset from a scalar base pointer.
 #include "common.h"
+#include "reaction.h"
 
 namespace adr {
 namespace {
@@ -277,14 +278,78 @@ __global__ __launch_bounds__(64 * WI * WX, 2) void k_mode_f64_grouped(const Tile
   mode_tile_f64<BI, BX, WI, WX, BK, KFAST, false>(job, itile, xtile, sM, sW);
 }
 
+// Epilogue of a V tile that carries ETD2RKds stage 2 (see k_mode_f64_persist),
+// for reaction model MODEL.  The six tensors are distinct buffers: the
+// restrict-qualified parameters let the loads of a batch of elements be issued
+// together, and ahead of the stores of the previous batch, so the epilogue
+// waits for memory about once per batch rather than once per element.
+template <int MODEL, int FI, int FX, typename Index>
+__device__ __forceinline__ void stage2_epilogue_m(const d4 (&acc)[FI][FX], double alpha, Index idx,
+                                                  const Reaction& r, double* __restrict__ V2,
+                                                  const double* __restrict__ U2,
+                                                  const double* __restrict__ Un,
+                                                  const double* __restrict__ Vn,
+                                                  double* __restrict__ Ru, double* __restrict__ Rv) {
+  constexpr int NE = FI * FX * 4;
+  constexpr int B = 8;  // elements per batch
+  static_assert(NE % B == 0, "batch size");
+#pragma unroll
+  for (int b0 = 0; b0 < NE; b0 += B) {
+    unsigned o[B];
+    double un[B], vn[B], u2[B];
+#pragma unroll
+    for (int e = 0; e < B; ++e) {
+      const int q = b0 + e;
+      o[e] = idx(q / (FX * 4), (q / 4) % FX, q % 4);
+      un[e] = Un[o[e]];
+      vn[e] = Vn[o[e]];
+      u2[e] = U2[o[e]];
+    }
+#pragma unroll
+    for (int e = 0; e < B; ++e) {
+      const int q = b0 + e;
+      const double v2 = alpha * acc[q / (FX * 4)][(q / 4) % FX][q % 4];
+      double gu, gv, gu2, gv2;
+      react_model<MODEL>(r, un[e], vn[e], gu, gv);
+      react_model<MODEL>(r, u2[e], v2, gu2, gv2);
+      V2[o[e]] = v2;
+      Ru[o[e]] = gu2 - gu;
+      Rv[o[e]] = gv2 - gv;
+    }
+  }
+}
+
+template <int FI, int FX, typename Index>
+__device__ __forceinline__ void stage2_epilogue(const d4 (&acc)[FI][FX], double alpha, Index idx,
+                                                const Reaction& r, double* V2, const double* U2,
+                                                const double* Un, const double* Vn, double* Ru,
+                                                double* Rv) {
+  switch (r.model) {
+    case 0: stage2_epilogue_m<0>(acc, alpha, idx, r, V2, U2, Un, Vn, Ru, Rv); break;
+    case 1: stage2_epilogue_m<1>(acc, alpha, idx, r, V2, U2, Un, Vn, Ru, Rv); break;
+    case 2: stage2_epilogue_m<2>(acc, alpha, idx, r, V2, U2, Un, Vn, Ru, Rv); break;
+    case 4: stage2_epilogue_m<4>(acc, alpha, idx, r, V2, U2, Un, Vn, Ru, Rv); break;
+    default: stage2_epilogue_m<3>(acc, alpha, idx, r, V2, U2, Un, Vn, Ru, Rv);
+  }
+}
+
 // Persistent variant for evenly tiled shapes (n % BI == 0, X % BX == 0,
 // 16-byte aligned rows): a grid of about two workgroups per CU walks the tiles,
 // loads move two doubles per lane, and the first k-chunk of the next tile is
 // fetched while the last chunk of the current one is multiplied, so tile
 // boundaries (epilogue stores, first loads) overlap with MFMA work.
-template <int BI, int BX, int WI, int WX, int BK, bool KFAST, int MINB = 2>
+//
+// S2 (ETD2RKds stage 2 in the epilogue, a.Rout set): the two tensors' tiles
+// alternate (U tile, then the V tile of the same rows and fibres) and every
+// workgroup owns an even number of consecutive tiles, so when a V tile ends the
+// same lanes have already stored the U values of the same elements.  The V
+// epilogue reads them back (same-lane read after write), evaluates the reaction
+// at the new and the old states and stores R^c = G^c(C_{n2}) - G^c(C_n) for both
+// components, which saves the separate pass over four FP64 tensors.
+template <int BI, int BX, int WI, int WX, int BK, bool KFAST, int MINB = 2, bool S2 = false>
 __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64_persist(ModeArgs a, int n_itiles,
                                                                         int n_xtiles, int ntiles) {
+  static_assert(!(S2 && KFAST), "stage 2 is carried by x-contiguous products only");
   constexpr int NT = 64 * WI * WX;
   constexpr int TI = BI / WI, TX = BX / WX;
   constexpr int FI = TI / 16, FX = TX / 16;
@@ -324,7 +389,8 @@ __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64_persist(ModeArg
   // tile sequence of this workgroup: XCD-contiguous ranges (see k_mode_f64)
   const int G = gridDim.x;
   const int b = blockIdx.x;
-  const int per = (ntiles + G - 1) / G;     // tiles per workgroup (upper bound)
+  int per = (ntiles + G - 1) / G;           // tiles per workgroup (upper bound)
+  if (S2) per += per & 1;                   // U/V tile pairs never split
   // workgroup b handles logical tiles base, base+1, ... within its XCD's range
   const int xcd = b % 8, slot = b / 8;
 
@@ -345,6 +411,15 @@ __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64_persist(ModeArg
   };
   auto tile_of = [&](int t) {
     TileDesc d;
+    if (S2) {  // tensor fastest: U tile, V tile, next row tile, ...
+      d.g = t & 1;
+      const int rest = t >> 1;
+      d.i0 = (rest % n_itiles) * BI;
+      d.x0 = (unsigned)(rest / n_itiles) * BX;
+      d.W = static_cast<const double*>(pick(a.W, d.g));
+      d.M = static_cast<const double*>(pick(a.M, d.g));
+      return d;
+    }
     const int itile = t % n_itiles;
     const int rest = t / n_itiles;
     d.i0 = itile * BI;
@@ -362,7 +437,7 @@ __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64_persist(ModeArg
   // little faster for mu < d and 3-4 % slower for the last direction of a
   // multi-dimensional tensor (R = 1), which keeps contiguous per-workgroup ranges.)
   const int slots = G / 8;
-  const bool paired = (G % 8 == 0) && n_itiles > 1 && slots % n_itiles == 0 &&
+  const bool paired = !S2 && (G % 8 == 0) && n_itiles > 1 && slots % n_itiles == 0 &&
                       ntiles % n_itiles == 0 && (a.R > 1 || a.L == 1);
   const int nu = ntiles / n_itiles;                        // fibre blocks (all tensors)
   const int groups = 8 * (slots / n_itiles);
@@ -505,6 +580,16 @@ __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64_persist(ModeArg
     }
 
     // epilogue of the current tile (the next tile's first chunk is already in LDS)
+    if (S2 && cur.g == 1) {
+      // V tile: V_{n2} = alpha*acc; U_{n2} was stored by these lanes one tile ago
+      stage2_epilogue<FI, FX>(acc, alpha, [&](int fi, int fx, int v) { return out_index(cur, fi, fx, v); },
+                              a.react, out, static_cast<const double*>(a.out[0]), a.Y[0], a.Y[1],
+                              static_cast<double*>(a.Rout[0]), static_cast<double*>(a.Rout[1]));
+      if (tn < 0) break;
+      cur = nxt;
+      ++k;
+      continue;
+    }
     const double* Ye = y_in_acc ? nullptr : static_cast<const double*>(pick(reinterpret_cast<const void* const*>(a.Y), cur.g));
 #pragma unroll
     for (int fi = 0; fi < FI; ++fi)
@@ -536,8 +621,8 @@ int device_cu_count() {
   return cus;
 }
 
-template <int BI, int BX, int WI, int WX, int BK>
-bool launch_persist(const ModeArgs& a, hipStream_t s, hipError_t& err) {
+template <int BI, int BX, int BK>
+bool persist_fits(const ModeArgs& a) {
   // evenly tiled, pair-aligned shapes only; a tile's fibres stay within one batch
   if (a.n % BI != 0 || a.n % BK != 0 || a.X % BX != 0) return false;
   if (a.L != 1 && a.L % BX != 0) return false;
@@ -545,6 +630,12 @@ bool launch_persist(const ModeArgs& a, hipStream_t s, hipError_t& err) {
   for (int g = 0; g < a.group; ++g)
     if ((reinterpret_cast<uintptr_t>(a.W[g]) | reinterpret_cast<uintptr_t>(a.M[g])) % 16 != 0)
       return false;
+  return true;
+}
+
+template <int BI, int BX, int WI, int WX, int BK>
+bool launch_persist(const ModeArgs& a, hipStream_t s, hipError_t& err) {
+  if (!persist_fits<BI, BX, BK>(a)) return false;
   const int n_itiles = a.n / BI;
   const long long n_xtiles = a.X / BX;
   const long long ntiles = (long long)a.group * n_itiles * n_xtiles;
@@ -552,7 +643,10 @@ bool launch_persist(const ModeArgs& a, hipStream_t s, hipError_t& err) {
   long long grid = 2LL * device_cu_count();
   if (grid > ntiles) grid = ntiles;
   constexpr int NT = 64 * WI * WX;
-  if (a.L == 1)
+  if (a.Rout[0])
+    hipLaunchKernelGGL((k_mode_f64_persist<BI, BX, WI, WX, BK, false, 2, true>), dim3((unsigned)grid),
+                       dim3(NT), 0, s, a, n_itiles, (int)n_xtiles, (int)ntiles);
+  else if (a.L == 1)
     hipLaunchKernelGGL((k_mode_f64_persist<BI, BX, WI, WX, BK, true>), dim3((unsigned)grid),
                        dim3(NT), 0, s, a, n_itiles, (int)n_xtiles, (int)ntiles);
   else
@@ -617,8 +711,21 @@ hipError_t launch_mode_grouped_f64(TileCfg cfg, bool kfast, const TileJob* jobs,
   }
 }
 
+bool mode_f64_stage2_fusable(const ModeArgs& a) {
+  if (a.group != 2 || a.L == 1 || !a.Y[0] || !a.Y[1] || !a.out[0] || !a.out[1]) return false;
+  if (a.alpha == 0.0) return false;
+  return a.n <= 64 ? persist_fits<64, 128, 16>(a) : persist_fits<128, 128, 16>(a);
+}
+
 hipError_t launch_mode_product_f64(const ModeArgs& a, hipStream_t s) {
   hipError_t e = hipSuccess;
+  if (a.Rout[0] || a.Rout[1]) {
+    // stage 2 in the epilogue: only the persistent x-contiguous kernels carry it
+    if (!a.Rout[0] || !a.Rout[1] || !mode_f64_stage2_fusable(a)) return hipErrorInvalidValue;
+    if (a.n <= 64) launch_persist<64, 128, 1, 4, 16>(a, s, e);
+    else launch_persist<128, 128, 2, 2, 16>(a, s, e);
+    return e;
+  }
   if (a.n <= 64) {
     if (launch_persist<64, 128, 1, 4, 16>(a, s, e)) return e;
     return launch_cfg<64, 128, 1, 4, 16>(a, s);

@@ -3,44 +3,10 @@
 // when A_mu is tridiagonal, and the combinations that feed the Tucker operators.
 // All are HBM-bound streaming kernels; the state U, V is FP64 throughout.
 #include "common.h"
+#include "reaction.h"
 
 namespace adr {
 namespace {
-
-// Reaction terms (the constants' order is documented in include/adr.h).
-__device__ __forceinline__ void react(const Reaction& r, double u, double v, double& gu,
-                                      double& gv) {
-  switch (r.model) {
-    case 0: {  // Schnakenberg: gamma(a - u + u^2 v), gamma(b - u^2 v)
-      const double u2v = u * u * v;
-      gu = r.p[0] * (r.p[1] - u + u2v);
-      gv = r.p[0] * (r.p[2] - u2v);
-      break;
-    }
-    case 1: {  // FitzHugh-Nagumo: rho(u - u^3 - v), rho eps(u - a1 v - a0)
-      gu = r.p[0] * (u - u * u * u - v);
-      gv = r.p[0] * r.p[1] * (u - r.p[2] * v - r.p[3]);
-      break;
-    }
-    case 2: {  // Brusselator: A - (B+1) u + u^2 v,  B u - u^2 v
-      const double u2v = u * u * v;
-      gu = r.p[0] - (r.p[1] + 1.0) * u + u2v;
-      gv = r.p[1] * u - u2v;
-      break;
-    }
-    case 4: {  // DIB: rho(a1u(1-v)u - a2u u^3 - a3u(v-a4u)),
-               //      rho(a1v(1+a2v u)(1-v)(1-a3v(1-v)) - a4v v(1+a5v u)(1+a3v v))
-      const double w = 1.0 - v;
-      gu = r.p[0] * (r.p[1] * w * u - r.p[2] * u * u * u - r.p[3] * (v - r.p[4]));
-      gv = r.p[0] * (r.p[5] * (1.0 + r.p[6] * u) * w * (1.0 - r.p[7] * w) -
-                     r.p[8] * v * (1.0 + r.p[9] * u) * (1.0 + r.p[7] * v));
-      break;
-    }
-    default:
-      gu = 0.0;
-      gv = 0.0;
-  }
-}
 
 template <typename T>
 __device__ __forceinline__ void put(void* p, long long q, double x) {

@@ -64,6 +64,11 @@ CASES = [
     # experiment of Sec. 4.5 (eq. (16), Gaussian-bump data) at its own 80^3 grid
     ("dib2d_96x80_40", S.with_shape(S.dib_2d(200, 1250), (96, 80)), 40),
     ("paper_schnak3d_80_10", S.paper_schnakenberg_3d(80, 50), 10),
+    # evenly tiled grids: the last product of the phi_1 operator also computes
+    # stage 2 (128-row tiles; 64-row tiles for n_d = 64)
+    ("schnakenberg2d_256x128_20", S.with_shape(S.schnakenberg_2d(), (256, 128)), 20),
+    ("bruss3d_64x128x64_10", S.with_shape(S.brusselator_3d(), (64, 128, 64)), 10),
+    ("dib2d_128x256_10", S.with_shape(S.dib_2d(200, 1250), (128, 256)), 10),
 ]
 
 
@@ -74,7 +79,7 @@ def test_etd2rkds_hot_path(dev, name, w, steps):
     _assert_close(got, (U, V), joint=(w.model == "dib"))
 
 
-E2E = CASES[:4] + [CASES[6]]
+E2E = CASES[:4] + [CASES[6], CASES[8]]
 
 
 @pytest.mark.parametrize("name,w,steps", E2E, ids=[c[0] for c in E2E])
