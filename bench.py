@@ -328,6 +328,10 @@ def main(argv=None):
     if args.precision == "f64" and args.scheme == "etd2rkds" and n_stage < 1.5 * args.steps:
         # one product per step also carries stage 2 (48 B/point), averaged over the 2d launches
         bytes_per_launch += 48 * N / (2 * d)
+    if args.precision != "f64" and args.scheme == "etd2rkds" and n_stage < 2.5 * args.steps:
+        # the last product forms C_{n+1} = (C_n + D1) + D2: per component it also reads
+        # C_n (8 B) and D1 (4 B) and writes FP64 (8 B) instead of FP32 (4 B)
+        bytes_per_launch += 2 * 16 * N / (2 * d)
     # split BF16: three products' MFMA time (3 x flops at 2.5 PFLOP/s) is below the
     # time to move its FP32 operands, so its roofline is HBM
     hbm_bound = args.precision == "bf16x3"
@@ -336,13 +340,13 @@ def main(argv=None):
     # algorithmic bytes per point of the stage kernels, averaged over the launches of a step:
     # FP64: stage 1 (read U,V; write R1u,R1v) 32 B, and stage 2 (read U,V,U2,V2; write R2)
     # 48 B unless the last product of the phi_1 operator carries it (then stage 1 only);
-    # reduced precision: stage 1 24 B (FP32 R1), stage 2 32 B (FP32 D1 in, R2 out),
-    # final C += D1 + D2 48 B
+    # reduced precision: stage 1 24 B (FP32 R1), stage 2 32 B (FP32 D1 in, R2 out)
+    # (the final C_{n+1} = C_n + D1 + D2 is formed by the last mode product)
     stage_per_step = n_stage / max(args.steps, 1)
     if args.precision == "f64":
         stage_bytes = (32.0 if stage_per_step < 1.5 else (32 + 48) / 2) * N
     else:
-        stage_bytes = (24 + 32 + 48) / 3 * N
+        stage_bytes = (24 + 32) / 2 * N
 
     line = {
         "metric": METRIC,

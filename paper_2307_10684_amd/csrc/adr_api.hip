@@ -33,6 +33,7 @@ struct TuckerGroup {
   const unsigned short* Ml[kMaxGroup][3] = {};
   void* out[kMaxGroup] = {};
   const double* Y[kMaxGroup] = {};
+  const float* Z[kMaxGroup] = {};   // reduced precision: FP32 second addend of the last product
   void* t1[kMaxGroup] = {};   // ping buffer
   void* t2[kMaxGroup] = {};   // pong buffer (may be the input when it may be clobbered)
 };
@@ -101,17 +102,21 @@ hipError_t run_tucker(const Geometry& g, const TuckerGroup& tg, double alpha, do
       const void* Mh[kMaxGroup];
       const void* Ml[kMaxGroup];
       const double* Y[kMaxGroup];
+      const float* Z[kMaxGroup];
+      bool with_z = false;
       for (int k = 0; k < tg.count; ++k) {
         Mf[k] = tg.M[k][mu];
         Mh[k] = tg.Mh[k][mu];
         Ml[k] = tg.Ml[k][mu];
         Y[k] = last ? tg.Y[k] : nullptr;
+        Z[k] = last ? tg.Z[k] : nullptr;
+        with_z = with_z || Z[k] != nullptr;
       }
       const long long X = g.N / g.n[mu];
       e = timed(kKindMode, s, [&] {
         return launch_tgemm_lowp(precision, W, Mf, Mh, Ml, out, Y, tg.count, g.n[mu], X,
                                  last ? alpha : 1.0, last ? beta : 0.0,
-                                 (last && !last_f32) ? 1 : 0, s);
+                                 (last && !last_f32) ? 1 : 0, s, with_z ? Z : nullptr);
       });
     }
     if (e != hipSuccess) return e;
@@ -308,18 +313,15 @@ hipError_t step_etd2rkds(const adr_problem* p, const Geometry& g, const Carve& c
                                    static_cast<float*>(c.R[1]), s);
     });
     if (e != hipSuccess) return e;
-    // D2 = 2^(d-1) tau * Tucker(R2; phi_2) into the buffer the chain does not read last
+    // C_{n+1} = (C_n + D1) + D2 with D2 = 2^(d-1) tau * Tucker(R2; phi_2): the last
+    // product adds its result to C_n + D1 in FP64 and writes C in place
     for (int cc = 0; cc < 2; ++cc) {
       for (int mu = 0; mu < g.d; ++mu) set_phi(tg, cc, p, c, cc, 2, mu);
-      tg.out[cc] = (g.d == 2) ? c.R[cc] : c.T[cc];
+      tg.out[cc] = cc == 0 ? static_cast<void*>(U) : static_cast<void*>(V);
+      tg.Y[cc] = cc == 0 ? U : V;
+      tg.Z[cc] = static_cast<const float*>(c.D[cc]);
     }
-    e = run_tucker(g, tg, std::ldexp(p->tau, g.d - 1), 0.0, p->precision, s, true);
-    if (e != hipSuccess) return e;
-    const float* D2u = static_cast<const float*>(tg.out[0]);
-    const float* D2v = static_cast<const float*>(tg.out[1]);
-    return timed(kKindStage, s, [&] {
-      return launch_etd_final_inc(g.N, U, V, c.D[0], c.D[1], D2u, D2v, s);
-    });
+    return run_tucker(g, tg, std::ldexp(p->tau, g.d - 1), 1.0, p->precision, s);
   }
   tg.out[0] = c.U2;
   tg.out[1] = c.V2;

@@ -76,16 +76,20 @@ hipError_t launch_mode_product_f64(const ModeArgs& a, hipStream_t s);
 //   out[x + X*i] = alpha * sum_k M[i,k] W[k + n*x] (+ beta * Y[x + X*i])
 // W: FP32 n x X column-major; M: FP32 n x n column-major (FP32) or transposed
 // bf16 hi/lo parts (BF16X3); out: FP32, or FP64 with the FP64 addend Y.
+// With the FP32 addends Z (FP64 output only):
+//   out = (beta * Y + Z) + alpha * sum_k M[i,k] W[k + n*x].
 hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* const* Mf32,
                              const void* const* Mh, const void* const* Ml, void* const* out,
                              const double* const* Y, int group, int n, long long X, double alpha,
-                             double beta, int out_f64, hipStream_t s);
+                             double beta, int out_f64, hipStream_t s,
+                             const float* const* Z = nullptr);
 // One FP32 transposing product of a grouped launch (tiles of 128 x 128).
 struct LowpJob {
   const float* W;
   const float* M;
   void* out;
   const double* Y;
+  const float* Z;          // FP32 second addend (FP64 output only), or null
   double alpha, beta;
   int n;
   long long X;
@@ -149,13 +153,10 @@ hipError_t launch_etd_stage2(long long N, const Reaction& r, const double* U, co
                              const double* U2, const double* V2, void* Ru, void* Rv, int r_f32,
                              hipStream_t s);
 // Reduced-precision ETD2RKds with FP32 increments D1, D2 of the two Tucker operators:
-// stage 2 R^c = G^c(U + D1u, V + D1v) - G^c(U, V); final C <- C + D1^c + D2^c.
+// stage 2 R^c = G^c(U + D1u, V + D1v) - G^c(U, V).
 hipError_t launch_etd_stage2_inc(long long N, const Reaction& r, const double* U, const double* V,
                                  const float* Du, const float* Dv, float* Ru, float* Rv,
                                  hipStream_t s);
-hipError_t launch_etd_final_inc(long long N, double* U, double* V, const float* D1u,
-                                const float* D1v, const float* D2u, const float* D2v,
-                                hipStream_t s);
 // Lawson2b stage 1: A^c = C + tau G^c(U, V), B^c = C + tau/2 G^c(U, V).
 hipError_t launch_lawson_stage1(long long N, const Reaction& r, double tau, const double* U,
                                 const double* V, void* Au, void* Av, void* Bu, void* Bv, int f32,

@@ -45,6 +45,7 @@ struct LowpArgs {
   const unsigned short* Ml[kMaxGroup];
   void* out[kMaxGroup];          // FP32 (rotated) or FP64 (last product)
   const double* Y[kMaxGroup];    // FP64 addend for the last product, may alias out
+  const float* Z[kMaxGroup];     // FP32 second addend of the last product, or null
   double alpha, beta;
   int n;
   unsigned X;
@@ -60,6 +61,7 @@ __device__ __forceinline__ LowpJob job_of(const LowpArgs& a, int g) {
   j.M = a.M[g];
   j.out = a.out[g];
   j.Y = a.Y[g];
+  j.Z = a.Z[g];
   j.alpha = a.alpha;
   j.beta = a.beta;
   j.n = a.n;
@@ -71,47 +73,112 @@ __device__ __forceinline__ LowpJob job_of(const LowpArgs& a, int g) {
 }
 
 // Epilogue of a wave's TI x TX block of D[i][x] (lane: rows 4*krow + v of each
-// 16x16 block, column col).  For the FP64 output all addends of one 16-column
-// strip are loaded before any result is formed, so their latencies overlap.
+// 16x16 block, column col).
+//
+// FP64 output (the last product of a chain): out = alpha*acc + beta*Y, or with
+// a second addend Z, (beta*Y + Z) + alpha*acc -- the last product of
+// reduced-precision ETD2RKds writes C_{n+1} = (C_n + D1) + D2 in place of C_n
+// without storing D2.  Y may alias out (each element is read, then written, by
+// the same lane), so the addends of strip fx + 1 are loaded, in program order,
+// before the results of strip fx are stored: one memory wait per strip, with
+// the next strip's loads in flight.  Loads use clamped indices (no branches);
+// only stores outside the tensor are masked, and a wave tile that lies wholly
+// inside it skips the masks.
+template <int FI, int FX, bool HASY, bool HASZ, bool GUARD>
+__device__ __forceinline__ void tgemm_epilogue64(const LowpJob& a, const f4 (&acc)[FI][FX], int ib,
+                                                 unsigned xb, int col, int krow) {
+  const int n = a.n;
+  const unsigned X = (unsigned)a.X;
+  const double alpha = a.alpha, beta = a.beta;
+  const double* Y = a.Y;
+  const float* Z = a.Z;
+  double* out = static_cast<double*>(a.out);
+  double y[2][FI][4];
+  float z[2][FI][4];
+  // outside the tensor the loads read a clamped (valid, lane-varying) element
+  auto index = [&](int fx, int fi, int v, bool& ok) {
+    unsigned x = xb + fx * 16 + col;
+    int i = ib + fi * 16 + 4 * krow + v;
+    ok = !GUARD || (x < X && i < n);
+    if (GUARD) {
+      x = min(x, X - 1);
+      i = min(i, n - 1);
+    }
+    return x + X * (unsigned)i;
+  };
+  auto load_strip = [&](int fx) {
+#pragma unroll
+    for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        bool ok;
+        const unsigned o = index(fx, fi, v, ok);
+        if (HASY) y[fx & 1][fi][v] = Y[o];
+        if (HASZ) z[fx & 1][fi][v] = Z[o];
+      }
+  };
+  load_strip(0);
+#pragma unroll
+  for (int fx = 0; fx < FX; ++fx) {
+    if (fx + 1 < FX) load_strip(fx + 1);
+#pragma unroll
+    for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        bool ok;
+        const unsigned o = index(fx, fi, v, ok);
+        const double p = alpha * (double)acc[fi][fx][v];
+        double val = p;
+        if (HASZ) val = ((HASY ? beta * y[fx & 1][fi][v] : 0.0) + (double)z[fx & 1][fi][v]) + p;
+        else if (HASY) val = p + beta * y[fx & 1][fi][v];
+        if (ok) out[o] = val;
+      }
+  }
+}
+
 template <int FI, int FX, int TI, int TX, bool OUT64>
 __device__ __forceinline__ void tgemm_epilogue(const LowpJob& a, const f4 (&acc)[FI][FX],
                                                int ib, unsigned xb, int col, int krow) {
   const int n = a.n;
   const unsigned X = (unsigned)a.X;
-  const double alpha = a.alpha, beta = a.beta;
-  const double* Y = a.Y;
+  if (OUT64) {
+    // ib and xb are the same in every lane of the wave: a scalar branch
+    const bool inside = __builtin_amdgcn_readfirstlane((int)(ib + TI <= n && xb + TX <= X)) != 0;
+    const bool hy = a.Y != nullptr, hz = a.Z != nullptr;
+    if (inside) {
+      if (hz) {
+        if (hy) tgemm_epilogue64<FI, FX, true, true, false>(a, acc, ib, xb, col, krow);
+        else tgemm_epilogue64<FI, FX, false, true, false>(a, acc, ib, xb, col, krow);
+      } else if (hy) {
+        tgemm_epilogue64<FI, FX, true, false, false>(a, acc, ib, xb, col, krow);
+      } else {
+        tgemm_epilogue64<FI, FX, false, false, false>(a, acc, ib, xb, col, krow);
+      }
+    } else {
+      if (hz) {
+        if (hy) tgemm_epilogue64<FI, FX, true, true, true>(a, acc, ib, xb, col, krow);
+        else tgemm_epilogue64<FI, FX, false, true, true>(a, acc, ib, xb, col, krow);
+      } else if (hy) {
+        tgemm_epilogue64<FI, FX, true, false, true>(a, acc, ib, xb, col, krow);
+      } else {
+        tgemm_epilogue64<FI, FX, false, false, true>(a, acc, ib, xb, col, krow);
+      }
+    }
+    return;
+  }
+  const double alpha = a.alpha;
+  float* out = static_cast<float*>(a.out);
 #pragma unroll
   for (int fx = 0; fx < FX; ++fx) {
     const unsigned x = xb + fx * 16 + col;
     const bool xok = x < X;
-    if (OUT64) {
-      double y[FI][4];
 #pragma unroll
-      for (int fi = 0; fi < FI; ++fi)
+    for (int fi = 0; fi < FI; ++fi)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = ib + fi * 16 + 4 * krow + v;
-          const bool ok = xok && i < n && Y != nullptr;
-          y[fi][v] = ok ? Y[x + X * (unsigned)i] : 0.0;
-        }
-      double* out = static_cast<double*>(a.out);
-#pragma unroll
-      for (int fi = 0; fi < FI; ++fi)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = ib + fi * 16 + 4 * krow + v;
-          if (xok && i < n) out[x + X * (unsigned)i] = alpha * (double)acc[fi][fx][v] + beta * y[fi][v];
-        }
-    } else {
-      float* out = static_cast<float*>(a.out);
-#pragma unroll
-      for (int fi = 0; fi < FI; ++fi)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i = ib + fi * 16 + 4 * krow + v;
-          if (xok && i < n) out[x + X * (unsigned)i] = (float)(alpha * (double)acc[fi][fx][v]);
-        }
-    }
+      for (int v = 0; v < 4; ++v) {
+        const int i = ib + fi * 16 + 4 * krow + v;
+        if (xok && i < n) out[x + X * (unsigned)i] = (float)(alpha * (double)acc[fi][fx][v]);
+      }
   }
 }
 
@@ -447,9 +514,9 @@ hipError_t launch_tiles(K kern, const LowpArgs& a, int BI, int BX, hipStream_t s
 hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* const* Mf32,
                              const void* const* Mh, const void* const* Ml, void* const* out,
                              const double* const* Y, int group, int n, long long X, double alpha,
-                             double beta, int out_f64, hipStream_t s) {
+                             double beta, int out_f64, hipStream_t s, const float* const* Z) {
   if (group < 1 || group > kMaxGroup || X <= 0 || X >= (1LL << 31) ||
-      (long long)n * X >= (1LL << 31))
+      (long long)n * X >= (1LL << 31) || (Z && !out_f64))
     return hipErrorInvalidValue;
   LowpArgs a{};
   for (int g = 0; g < group; ++g) {
@@ -459,6 +526,7 @@ hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* co
     a.Ml[g] = Ml ? static_cast<const unsigned short*>(Ml[g]) : nullptr;
     a.out[g] = out[g];
     a.Y[g] = Y ? Y[g] : nullptr;
+    a.Z[g] = Z ? Z[g] : nullptr;
   }
   a.alpha = alpha;
   a.beta = beta;

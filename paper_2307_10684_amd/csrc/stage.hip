@@ -364,7 +364,8 @@ __global__ __launch_bounds__(256) void k_etd_stage2(long long N, Reaction r,
 // Reduced-precision ETD2RKds keeps the Tucker results as FP32 increments
 // D1 = tau T1, D2 = 2^(d-1) tau T2 and forms the FP64 states pointwise:
 // stage 2: R^c = G^c(U + D1u, V + D1v) - G^c(U, V);
-// final:   C <- C + D1^c + D2^c   (i.e. C_{n+1} = C_{n2} + D2 with C_{n2} = C_n + D1).
+// the final C_{n+1} = (C_n + D1) + D2 is formed by the last product of the
+// phi_2 operator (its FP32 second addend) or, in grouped plans, pointwise.
 __global__ __launch_bounds__(256) void k_etd_stage2_inc(long long N, Reaction r,
                                                         const double* __restrict__ U,
                                                         const double* __restrict__ V,
@@ -380,19 +381,6 @@ __global__ __launch_bounds__(256) void k_etd_stage2_inc(long long N, Reaction r,
     react(r, u + (double)Du[q], v + (double)Dv[q], gu2, gv2);
     Ru[q] = (float)(gu2 - gu);
     Rv[q] = (float)(gv2 - gv);
-  }
-}
-
-__global__ __launch_bounds__(256) void k_etd_final_inc(long long N, double* __restrict__ U,
-                                                       double* __restrict__ V,
-                                                       const float* __restrict__ D1u,
-                                                       const float* __restrict__ D1v,
-                                                       const float* __restrict__ D2u,
-                                                       const float* __restrict__ D2v) {
-  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < N;
-       q += (long long)gridDim.x * blockDim.x) {
-    U[q] = (U[q] + (double)D1u[q]) + (double)D2u[q];
-    V[q] = (V[q] + (double)D1v[q]) + (double)D2v[q];
   }
 }
 
@@ -502,14 +490,6 @@ hipError_t launch_etd_stage2_inc(long long N, const Reaction& r, const double* U
                                  hipStream_t s) {
   hipLaunchKernelGGL(k_etd_stage2_inc, dim3(stream_grid(N)), dim3(256), 0, s, N, r, U, V, Du, Dv,
                      Ru, Rv);
-  return hipGetLastError();
-}
-
-hipError_t launch_etd_final_inc(long long N, double* U, double* V, const float* D1u,
-                                const float* D1v, const float* D2u, const float* D2v,
-                                hipStream_t s) {
-  hipLaunchKernelGGL(k_etd_final_inc, dim3(stream_grid(N)), dim3(256), 0, s, N, U, V, D1u, D1v,
-                     D2u, D2v);
   return hipGetLastError();
 }
 
