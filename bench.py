@@ -292,6 +292,7 @@ def main(argv=None):
     elapsed_ev = time.perf_counter() - t1
     n_mode, ms_mode = adr.adr_timing_read(0)
     n_stage, ms_stage = adr.adr_timing_read(1)
+    n_fused, ms_fused = adr.adr_timing_read(3)
     adr.adr_timing_enable(0)
 
     if not args.no_extras:
@@ -325,13 +326,12 @@ def main(argv=None):
             "bf16x3": PEAKS["bf16_mfma_tflops"]}[args.precision]
     achieved = flops_per_launch / (mode_avg_ms * 1e-3) / 1e12
     bytes_per_launch = 2 * 2 * elem * N  # read + write one tensor per component
-    if args.precision == "f64" and args.scheme == "etd2rkds" and n_stage < 1.5 * args.steps:
-        # one product per step also carries stage 2 (48 B/point), averaged over the 2d launches
-        bytes_per_launch += 48 * N / (2 * d)
-    if args.precision != "f64" and args.scheme == "etd2rkds" and n_stage < 2.5 * args.steps:
-        # the last product forms C_{n+1} = (C_n + D1) + D2: per component it also reads
-        # C_n (8 B) and D1 (4 B) and writes FP64 (8 B) instead of FP32 (4 B)
-        bytes_per_launch += 2 * 16 * N / (2 * d)
+    # the product launch of a step whose epilogue also computes a stage (timed apart),
+    # 32 B/point more than a plain launch in both cases: FP64 reads the states C_n
+    # (16 B) and writes R2 (16 B); reduced precision reads C_n (16 B) and D1 (8 B) and
+    # writes FP64 instead of FP32 (8 B)
+    fused_avg_ms = ms_fused / n_fused if n_fused else None
+    fused_bytes = bytes_per_launch + 32 * N
     # split BF16: three products' MFMA time (3 x flops at 2.5 PFLOP/s) is below the
     # time to move its FP32 operands, so its roofline is HBM
     hbm_bound = args.precision == "bf16x3"
@@ -378,6 +378,16 @@ def main(argv=None):
             "launches": n_mode,
             "flops_per_launch": flops_per_launch,
             "algorithmic_bytes_per_launch": bytes_per_launch,
+            "fused_launch": None if fused_avg_ms is None else {
+                "what": ("last product of the phi_1 operator, stage 2 in its epilogue"
+                         if args.precision == "f64" else
+                         "last product of the phi_2 operator, writes C_n + D1 + D2 in FP64"),
+                "launches": n_fused,
+                "avg_launch_ms": fused_avg_ms,
+                "tflops": flops_per_launch / (fused_avg_ms * 1e-3) / 1e12,
+                "algorithmic_bytes_per_launch": fused_bytes,
+                "hbm_gbs": fused_bytes / (fused_avg_ms * 1e-3) / 1e9,
+            },
         },
         "stage_kernels": {
             "bound": "hbm",

@@ -290,9 +290,11 @@ int adr_batch_destroy(adr_batch* plan);
  * Batch plans run without a graph are timed the same way, one record per
  * grouped launch.
  * adr_timing_read synchronises on the recorded events and returns, for the
- * kernel class `kind` (0 = mode product, 1 = stage kernels, 2 = all), the
- * number of launches and their summed duration in milliseconds, then clears
- * the record.  Not thread-safe; intended for benchmarks.
+ * kernel class `kind` (0 = mode products, 1 = stage kernels, 2 = all,
+ * 3 = mode products whose epilogue also computes a stage: ETD2RKds stage 2 in
+ * FP64, the new state in reduced precision), the number of launches and their
+ * summed duration in milliseconds.  The record is kept until the next
+ * adr_timing_enable.  Not thread-safe; intended for benchmarks.
  */
 int adr_timing_enable(int capacity);
 int adr_timing_read(int kind, int* launches, double* total_ms);

@@ -96,7 +96,8 @@ hipError_t run_tucker(const Geometry& g, const TuckerGroup& tg, double alpha, do
         a.Rout[1] = fuse->R[1];
         a.react = fuse->r;
       }
-      e = timed(kKindMode, s, [&] { return launch_mode_product_f64(a, s); });
+      e = timed((last && fuse) ? kKindModeFused : kKindMode, s,
+                [&] { return launch_mode_product_f64(a, s); });
     } else {
       const void* Mf[kMaxGroup];
       const void* Mh[kMaxGroup];
@@ -113,7 +114,7 @@ hipError_t run_tucker(const Geometry& g, const TuckerGroup& tg, double alpha, do
         with_z = with_z || Z[k] != nullptr;
       }
       const long long X = g.N / g.n[mu];
-      e = timed(kKindMode, s, [&] {
+      e = timed(with_z ? kKindModeFused : kKindMode, s, [&] {
         return launch_tgemm_lowp(precision, W, Mf, Mh, Ml, out, Y, tg.count, g.n[mu], X,
                                  last ? alpha : 1.0, last ? beta : 0.0,
                                  (last && !last_f32) ? 1 : 0, s, with_z ? Z : nullptr);
@@ -805,7 +806,7 @@ int adr_timing_enable(int capacity) {
 }
 
 int adr_timing_read(int kind, int* launches, double* total_ms) {
-  if (!launches || !total_ms || kind < 0 || kind > 2) return ADR_EINVAL;
+  if (!launches || !total_ms || kind < 0 || kind > 3) return ADR_EINVAL;
   Timing& t = g_timing;
   int cnt = 0;
   double tot = 0.0;

@@ -284,14 +284,15 @@ __global__ __launch_bounds__(64 * WI * WX, 2) void k_mode_f64_grouped(const Tile
 // together, and ahead of the stores of the previous batch, so the epilogue
 // waits for memory about once per batch rather than once per element.
 template <int MODEL, int FI, int FX, typename Index>
-__device__ __forceinline__ void stage2_epilogue_m(const d4 (&acc)[FI][FX], double alpha, Index idx,
+__device__ __forceinline__ void stage2_epilogue_m(const d4 (&acc)[FI][FX], double alpha,
+                                                  double beta, Index idx,
                                                   const Reaction& r, double* __restrict__ V2,
                                                   const double* __restrict__ U2,
                                                   const double* __restrict__ Un,
                                                   const double* __restrict__ Vn,
                                                   double* __restrict__ Ru, double* __restrict__ Rv) {
   constexpr int NE = FI * FX * 4;
-  constexpr int B = 8;  // elements per batch
+  constexpr int B = 4;  // elements per batch
   static_assert(NE % B == 0, "batch size");
 #pragma unroll
   for (int b0 = 0; b0 < NE; b0 += B) {
@@ -308,7 +309,7 @@ __device__ __forceinline__ void stage2_epilogue_m(const d4 (&acc)[FI][FX], doubl
 #pragma unroll
     for (int e = 0; e < B; ++e) {
       const int q = b0 + e;
-      const double v2 = alpha * acc[q / (FX * 4)][(q / 4) % FX][q % 4];
+      const double v2 = alpha * acc[q / (FX * 4)][(q / 4) % FX][q % 4] + beta * vn[e];
       double gu, gv, gu2, gv2;
       react_model<MODEL>(r, un[e], vn[e], gu, gv);
       react_model<MODEL>(r, u2[e], v2, gu2, gv2);
@@ -320,16 +321,17 @@ __device__ __forceinline__ void stage2_epilogue_m(const d4 (&acc)[FI][FX], doubl
 }
 
 template <int FI, int FX, typename Index>
-__device__ __forceinline__ void stage2_epilogue(const d4 (&acc)[FI][FX], double alpha, Index idx,
+__device__ __forceinline__ void stage2_epilogue(const d4 (&acc)[FI][FX], double alpha, double beta,
+                                                Index idx,
                                                 const Reaction& r, double* V2, const double* U2,
                                                 const double* Un, const double* Vn, double* Ru,
                                                 double* Rv) {
   switch (r.model) {
-    case 0: stage2_epilogue_m<0>(acc, alpha, idx, r, V2, U2, Un, Vn, Ru, Rv); break;
-    case 1: stage2_epilogue_m<1>(acc, alpha, idx, r, V2, U2, Un, Vn, Ru, Rv); break;
-    case 2: stage2_epilogue_m<2>(acc, alpha, idx, r, V2, U2, Un, Vn, Ru, Rv); break;
-    case 4: stage2_epilogue_m<4>(acc, alpha, idx, r, V2, U2, Un, Vn, Ru, Rv); break;
-    default: stage2_epilogue_m<3>(acc, alpha, idx, r, V2, U2, Un, Vn, Ru, Rv);
+    case 0: stage2_epilogue_m<0>(acc, alpha, beta, idx, r, V2, U2, Un, Vn, Ru, Rv); break;
+    case 1: stage2_epilogue_m<1>(acc, alpha, beta, idx, r, V2, U2, Un, Vn, Ru, Rv); break;
+    case 2: stage2_epilogue_m<2>(acc, alpha, beta, idx, r, V2, U2, Un, Vn, Ru, Rv); break;
+    case 4: stage2_epilogue_m<4>(acc, alpha, beta, idx, r, V2, U2, Un, Vn, Ru, Rv); break;
+    default: stage2_epilogue_m<3>(acc, alpha, beta, idx, r, V2, U2, Un, Vn, Ru, Rv);
   }
 }
 
@@ -340,9 +342,9 @@ __device__ __forceinline__ void stage2_epilogue(const d4 (&acc)[FI][FX], double 
 // boundaries (epilogue stores, first loads) overlap with MFMA work.
 //
 // S2 (ETD2RKds stage 2 in the epilogue, a.Rout set): the two tensors' tiles
-// alternate (U tile, then the V tile of the same rows and fibres) and every
-// workgroup owns an even number of consecutive tiles, so when a V tile ends the
-// same lanes have already stored the U values of the same elements.  The V
+// alternate (U tile, then the V tile of the same rows and fibres) within each
+// workgroup's sequence, so when a V tile ends the same lanes have already
+// stored the U values of the same elements.  The V
 // epilogue reads them back (same-lane read after write), evaluates the reaction
 // at the new and the old states and stores R^c = G^c(C_{n2}) - G^c(C_n) for both
 // components, which saves the separate pass over four FP64 tensors.
@@ -409,13 +411,39 @@ __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64_persist(ModeArg
     p = g == 3 ? arr[3] : p;
     return p;
   };
+  // logical tile k of this workgroup (k = 0, 1, ...); -1 when done.
+  // When the workgroups of an XCD can be grouped n_itiles at a time, the group
+  // members take the n_itiles row tiles of the same fibre blocks in lockstep:
+  // they read the same W chunks at about the same time, so the XCD's L2 serves
+  // the repeats and W is fetched from HBM about once.  (Measured at 256^3: a
+  // little faster for mu < d and 3-4 % slower for the last direction of a
+  // multi-dimensional tensor (R = 1), which keeps contiguous per-workgroup ranges;
+  // the product that carries stage 2 reads more and pairs.)
+  const int slots = G / 8;
+  const bool paired = (G % 8 == 0) && n_itiles > 1 && slots % n_itiles == 0 &&
+                      ntiles % n_itiles == 0 && (S2 || a.R > 1 || a.L == 1);
+  const int nu = ntiles / n_itiles;                        // fibre blocks (all tensors)
+  const int groups = 8 * (slots / n_itiles);
+  int per_u = (nu + groups - 1) / groups;                  // fibre blocks per group
+  if (S2) per_u += per_u & 1;                              // U/V block pairs never split
   auto tile_of = [&](int t) {
     TileDesc d;
-    if (S2) {  // tensor fastest: U tile, V tile, next row tile, ...
-      d.g = t & 1;
-      const int rest = t >> 1;
-      d.i0 = (rest % n_itiles) * BI;
-      d.x0 = (unsigned)(rest / n_itiles) * BX;
+    if (S2) {
+      // paired: fibre block u = g + 2 * xtile, so a group member's blocks alternate
+      // U, V of the same fibres; otherwise tensor fastest: U tile, V tile, next
+      // row tile, ...
+      int itile, u;
+      if (paired) {
+        itile = t % n_itiles;
+        u = t / n_itiles;
+        d.g = u & 1;
+      } else {
+        d.g = t & 1;
+        itile = (t >> 1) % n_itiles;
+        u = (t >> 1) / n_itiles * 2;
+      }
+      d.i0 = itile * BI;
+      d.x0 = (unsigned)(u >> 1) * BX;
       d.W = static_cast<const double*>(pick(a.W, d.g));
       d.M = static_cast<const double*>(pick(a.M, d.g));
       return d;
@@ -429,19 +457,6 @@ __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64_persist(ModeArg
     d.M = static_cast<const double*>(pick(a.M, d.g));
     return d;
   };
-  // logical tile k of this workgroup (k = 0, 1, ...); -1 when done.
-  // When the workgroups of an XCD can be grouped n_itiles at a time, the group
-  // members take the n_itiles row tiles of the same fibre blocks in lockstep:
-  // they read the same W chunks at about the same time, so the XCD's L2 serves
-  // the repeats and W is fetched from HBM about once.  (Measured at 256^3: a
-  // little faster for mu < d and 3-4 % slower for the last direction of a
-  // multi-dimensional tensor (R = 1), which keeps contiguous per-workgroup ranges.)
-  const int slots = G / 8;
-  const bool paired = !S2 && (G % 8 == 0) && n_itiles > 1 && slots % n_itiles == 0 &&
-                      ntiles % n_itiles == 0 && (a.R > 1 || a.L == 1);
-  const int nu = ntiles / n_itiles;                        // fibre blocks (all tensors)
-  const int groups = 8 * (slots / n_itiles);
-  const int per_u = (nu + groups - 1) / groups;            // fibre blocks per group
   auto tile_index = [&](int k) {
     if (paired) {
       const int u = (xcd * (slots / n_itiles) + slot / n_itiles) * per_u + k;
@@ -528,7 +543,8 @@ __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64_persist(ModeArg
     const double* Y = y_in_acc ? static_cast<const double*>(pick(reinterpret_cast<const void* const*>(a.Y), cur.g)) : nullptr;
     const double* Z = static_cast<const double*>(pick(reinterpret_cast<const void* const*>(a.Z), cur.g));
     d4 acc[FI][FX];
-    if (!KFAST && Y) {
+    // (a V tile that carries stage 2 reads V_n in its epilogue anyway and adds it there)
+    if (!KFAST && Y && !(S2 && cur.g == 1)) {
       const double ys = beta / alpha;
 #pragma unroll
       for (int fi = 0; fi < FI; ++fi)
@@ -581,8 +597,9 @@ __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64_persist(ModeArg
 
     // epilogue of the current tile (the next tile's first chunk is already in LDS)
     if (S2 && cur.g == 1) {
-      // V tile: V_{n2} = alpha*acc; U_{n2} was stored by these lanes one tile ago
-      stage2_epilogue<FI, FX>(acc, alpha, [&](int fi, int fx, int v) { return out_index(cur, fi, fx, v); },
+      // V tile: V_{n2} = alpha*acc + beta*V_n; U_{n2} was stored by these lanes
+      // when they finished the U tile of the same rows and fibres
+      stage2_epilogue<FI, FX>(acc, alpha, beta, [&](int fi, int fx, int v) { return out_index(cur, fi, fx, v); },
                               a.react, out, static_cast<const double*>(a.out[0]), a.Y[0], a.Y[1],
                               static_cast<double*>(a.Rout[0]), static_cast<double*>(a.Rout[1]));
       if (tn < 0) break;
