@@ -140,6 +140,13 @@ def test_other_entry_points_validate(adr):
     assert lib.adr_device_copy(None, 4096, 8, None) == adr.ADR_EINVAL
     assert lib.adr_timing_enable(-1) == adr.ADR_EINVAL
     assert lib.adr_timing_enable(0) == adr.ADR_OK
+    # timing classes 0..3 (3: products whose epilogue also computes a stage)
+    cnt, tot = ctypes.c_int(-1), ctypes.c_double(-1.0)
+    for kind in range(4):
+        assert lib.adr_timing_read(kind, ctypes.byref(cnt), ctypes.byref(tot)) == adr.ADR_OK
+        assert cnt.value == 0 and tot.value == 0.0
+    assert lib.adr_timing_read(4, ctypes.byref(cnt), ctypes.byref(tot)) == adr.ADR_EINVAL
+    assert lib.adr_timing_read(-1, ctypes.byref(cnt), ctypes.byref(tot)) == adr.ADR_EINVAL
 
 
 def test_strerror_covers_all_codes(adr):
