@@ -45,9 +45,13 @@ MODE_SRC = {"f64": "mode_product_f64.hip", "f32": "mode_product_lowp.hip",
 
 
 def _src_hash(name: str) -> str:
+    """Hash of a kernel source's code: line comments and blank lines are dropped,
+    so a counter summary stays valid across comment-only edits."""
     path = os.path.join(ROOT, "paper_2307_10684_amd", "csrc", name)
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    with open(path, encoding="utf-8") as f:
+        lines = [ln.split("//", 1)[0].rstrip() for ln in f]
+    code = "\n".join(ln for ln in lines if ln)
+    return hashlib.sha256(code.encode()).hexdigest()[:16]
 
 
 def _traffic_from_profiles(precision: str, workload: str):

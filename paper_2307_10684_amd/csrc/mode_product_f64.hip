@@ -282,7 +282,8 @@ __global__ __launch_bounds__(64 * WI * WX, 2) void k_mode_f64_grouped(const Tile
 // for reaction model MODEL.  The six tensors are distinct buffers: the
 // restrict-qualified parameters let the loads of a batch of elements be issued
 // together, and ahead of the stores of the previous batch, so the epilogue
-// waits for memory about once per batch rather than once per element.
+// waits for memory about once per batch rather than once per element (a batch
+// of 4 keeps the kernel within 256 VGPRs; 8 spilled).
 template <int MODEL, int FI, int FX, typename Index>
 __device__ __forceinline__ void stage2_epilogue_m(const d4 (&acc)[FI][FX], double alpha,
                                                   double beta, Index idx,
@@ -344,10 +345,11 @@ __device__ __forceinline__ void stage2_epilogue(const d4 (&acc)[FI][FX], double 
 // S2 (ETD2RKds stage 2 in the epilogue, a.Rout set): the two tensors' tiles
 // alternate (U tile, then the V tile of the same rows and fibres) within each
 // workgroup's sequence, so when a V tile ends the same lanes have already
-// stored the U values of the same elements.  The V
-// epilogue reads them back (same-lane read after write), evaluates the reaction
-// at the new and the old states and stores R^c = G^c(C_{n2}) - G^c(C_n) for both
-// components, which saves the separate pass over four FP64 tensors.
+// stored the U values of the same elements.  The V epilogue reads them back
+// (same-lane read after write), adds V_n (not folded into its accumulators),
+// evaluates the reaction at the new and the old states and stores
+// R^c = G^c(C_{n2}) - G^c(C_n) for both components, which saves the separate
+// pass over four FP64 tensors.
 template <int BI, int BX, int WI, int WX, int BK, bool KFAST, int MINB = 2, bool S2 = false>
 __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64_persist(ModeArgs a, int n_itiles,
                                                                         int n_xtiles, int ntiles) {
