@@ -37,9 +37,10 @@ __device__ __forceinline__ void xcd_block(int& bx, int& by, int& bz) {
 // Stage 1 on LDS tiles.  A block of 64 x 4 threads owns a tile of kTX = 64
 // values of i_1 by kTY = 16 rows of i_2 and marches through ZB planes of i_3.
 // The plane being computed sits in LDS with a one-point halo in i_1 and i_2
-// (zero outside the grid, where the band coefficient is zero too); its i_3
-// neighbours are the previous and next planes' values of the thread's own
-// points, held in registers.  The loads of the plane after next are issued
+// (zero outside the grid, where the band coefficient is zero too); two LDS
+// buffers let the next plane be written while this one is read, with one
+// barrier per plane.  Its i_3 neighbours are the previous and next planes'
+// values of the thread's own points, held in registers.  The loads of the plane after next are issued
 // before the current plane is computed, so the compute of one plane covers
 // the memory latency of the loads for a later one.  Every value of the tile is
 // read from HBM once per plane; halos come from neighbouring tiles (L2).
@@ -57,8 +58,8 @@ __device__ __forceinline__ void etd_stage1_tile(const StageGeom& g, const Reacti
   const int z0 = bz * ZB, z1 = min(z0 + ZB, n3);
   const unsigned P = (unsigned)n1 * (unsigned)n2;
 
-  __shared__ double sU[kTY + 2][kTX + 2];
-  __shared__ double sV[kTY + 2][kTX + 2];
+  __shared__ double sU[2][kTY + 2][kTX + 2];   // double-buffered planes
+  __shared__ double sV[2][kTY + 2][kTX + 2];
   __shared__ double sb2[2][3][kTY];
   __shared__ double sb3[2][3][ZB];
 
@@ -124,15 +125,16 @@ __device__ __forceinline__ void etd_stage1_tile(const StageGeom& g, const Reacti
     hu = (zok && h_ok) ? a : 0.0;
     hv = (zok && h_ok) ? b : 0.0;
   };
-  auto to_lds = [&](const double (&iu)[kRows], const double (&iv)[kRows], double hu, double hv) {
+  auto to_lds = [&](int buf, const double (&iu)[kRows], const double (&iv)[kRows], double hu,
+                    double hv) {
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
-      sU[ty + 4 * k + 1][tx + 1] = iu[k];
-      sV[ty + 4 * k + 1][tx + 1] = iv[k];
+      sU[buf][ty + 4 * k + 1][tx + 1] = iu[k];
+      sV[buf][ty + 4 * k + 1][tx + 1] = iv[k];
     }
     if (has_halo) {
-      sU[h_r][h_c] = hu;
-      sV[h_r][h_c] = hv;
+      sU[buf][h_r][h_c] = hu;
+      sV[buf][h_r][h_c] = hv;
     }
   };
 
@@ -141,23 +143,28 @@ __device__ __forceinline__ void etd_stage1_tile(const StageGeom& g, const Reacti
   load_plane(z0 - 1, pu, pv, dummy_u, dummy_v);
   load_plane(z0, cu, cv, hcu, hcv);
   load_plane(z0 + 1, nu, nv, hnu, hnv);
-  to_lds(cu, cv, hcu, hcv);
+  to_lds(0, cu, cv, hcu, hcv);
   __syncthreads();
 
+  int buf = 0;
   for (int z = z0; z < z1; ++z) {
-    // loads of plane z + 2, in flight during this plane's compute
+    // loads of plane z + 2, in flight during this plane's compute; plane z + 1
+    // goes to the other LDS buffer (its readers finished before the last barrier)
     double lu[kRows], lv[kRows], lhu, lhv;
     const bool more = z + 1 < z1;
-    if (more) load_plane(z + 2, lu, lv, lhu, lhv);
+    if (more) {
+      load_plane(z + 2, lu, lv, lhu, lhv);
+      to_lds(buf ^ 1, nu, nv, hnu, hnv);
+    }
     const int zz = z - z0;
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
       const int ly = ty + 4 * k + 1, lx = tx + 1;
       const double uc = cu[k], vc = cv[k];
-      const double um = sU[ly][lx - 1], uq = sU[ly][lx + 1];
-      const double vm = sV[ly][lx - 1], vq = sV[ly][lx + 1];
-      const double uym = sU[ly - 1][lx], uyp = sU[ly + 1][lx];
-      const double vym = sV[ly - 1][lx], vyp = sV[ly + 1][lx];
+      const double um = sU[buf][ly][lx - 1], uq = sU[buf][ly][lx + 1];
+      const double vm = sV[buf][ly][lx - 1], vq = sV[buf][ly][lx + 1];
+      const double uym = sU[buf][ly - 1][lx], uyp = sU[buf][ly + 1][lx];
+      const double vym = sV[buf][ly - 1][lx], vyp = sV[buf][ly + 1][lx];
       const int yy = ty + 4 * k;
       double gu, gv;
       react(r, uc, vc, gu, gv);
@@ -174,9 +181,8 @@ __device__ __forceinline__ void etd_stage1_tile(const StageGeom& g, const Reacti
       }
     }
     if (!more) break;
-    __syncthreads();          // everyone is done with plane z in LDS
-    to_lds(nu, nv, hnu, hnv);  // plane z + 1
-    __syncthreads();
+    __syncthreads();  // plane z + 1 is in LDS and everyone is done with plane z
+    buf ^= 1;
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
       pu[k] = cu[k];
