@@ -69,6 +69,9 @@ CASES = [
     ("schnakenberg2d_256x128_20", S.with_shape(S.schnakenberg_2d(), (256, 128)), 20),
     ("bruss3d_64x128x64_10", S.with_shape(S.brusselator_3d(), (64, 128, 64)), 10),
     ("dib2d_128x256_10", S.with_shape(S.dib_2d(200, 1250), (128, 256)), 10),
+    # n % 64 == 0 but not % 128: 64-row persistent tiles (and stage 2 on them)
+    ("schnakenberg2d_128x192_20", S.with_shape(S.schnakenberg_2d(), (128, 192)), 20),
+    ("fhn3d_192x128x64_5", S.with_shape(S.fhn_3d(), (192, 128, 64)), 5),
 ]
 
 
