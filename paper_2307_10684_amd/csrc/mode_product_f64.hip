@@ -748,14 +748,19 @@ hipError_t launch_mode_product_f64(const ModeArgs& a, hipStream_t s) {
   // 64-row persistent tiles where 128-row ones would be ragged (n % 128 != 0,
   // n % 64 == 0): at 192^3 they run at 39 TFLOP/s against 30 for ragged
   // one-tile-per-workgroup 128-row tiles (measured)
-  if (a.n <= 64 || a.n % 128 != 0) {
-    if (launch_persist<64, 128, 1, 4, 16>(a, s, e)) return e;
-    if (a.n <= 64) return launch_cfg<64, 128, 1, 4, 16>(a, s);
-  }
+  if ((a.n <= 64 || a.n % 128 != 0) && launch_persist<64, 128, 1, 4, 16>(a, s, e)) return e;
   // fibre-contiguous products (L = 1) run best with a 2 x 4 wave grid (64 x 32
   // per wave), the others with 2 x 2 (64 x 64 per wave), measured at 256^3
   if (a.L == 1 && launch_persist<128, 128, 2, 4, 16>(a, s, e)) return e;
   if (a.L != 1 && launch_persist<128, 128, 2, 2, 16>(a, s, e)) return e;
+  // strided products whose L is a multiple of 64 but not of 128 (a tile's
+  // fibres must stay within one batch): 64-wide persistent tiles (192^3,
+  // mu = 2: 41 TFLOP/s against 30)
+  if (a.L != 1 && a.L % 64 == 0) {
+    if (a.n % 128 == 0 && launch_persist<128, 64, 2, 2, 16>(a, s, e)) return e;
+    if (launch_persist<64, 64, 2, 2, 16>(a, s, e)) return e;
+  }
+  if (a.n <= 64) return launch_cfg<64, 128, 1, 4, 16>(a, s);
   return launch_cfg<128, 128, 2, 2, 16>(a, s);
 }
 

@@ -72,6 +72,8 @@ CASES = [
     # n % 64 == 0 but not % 128: 64-row persistent tiles (and stage 2 on them)
     ("schnakenberg2d_128x192_20", S.with_shape(S.schnakenberg_2d(), (128, 192)), 20),
     ("fhn3d_192x128x64_5", S.with_shape(S.fhn_3d(), (192, 128, 64)), 5),
+    # strided direction with L % 128 != 0, L % 64 == 0: 64-wide persistent tiles
+    ("bruss3d_64x192x48_5", S.with_shape(S.brusselator_3d(), (64, 192, 48)), 5),
 ]
 
 
