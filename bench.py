@@ -145,8 +145,30 @@ def _lowp_legs(adr, S, torch, w, steps, seed, ref_state):
             Ur, Vr = ref_state
             err = max(float((Ud2 - Ur).abs().max() / Ur.abs().max()),
                       float((Vd2 - Vr).abs().max() / Vr.abs().max()))
+        # a separate pass with HIP events around each launch: the products' roofline
+        d = len(w.n)
+        adr.adr_timing_enable(steps * (2 * d + 4) + 8)
+        solver.solve(Ud, Vd, steps)
+        torch.cuda.synchronize()
+        n_mode, ms_mode = adr.adr_timing_read(0)
+        n_fused, ms_fused = adr.adr_timing_read(3)
+        adr.adr_timing_enable(0)
+        avg = ms_mode / max(n_mode, 1)
+        flops = 2 * 2.0 * (sum(w.n) / d) * w.N
+        nbytes = 2 * 2 * 4 * w.N
+        tf = flops / (avg * 1e-3) / 1e12
+        gbs = nbytes / (avg * 1e-3) / 1e9
+        if prec == "f32":
+            roof = {"bound": "mfma", "achieved": tf, "peak": PEAKS["f32_mfma_tflops"], "unit": "TFLOP/s",
+                    "frac": tf / PEAKS["f32_mfma_tflops"]}
+        else:
+            roof = {"bound": "hbm", "achieved": gbs, "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
+                    "frac": gbs / PEAKS["hbm_gbs"], "tflops_fp32_equivalent": tf}
+        roof.update({"kernel": f"mode_product_{prec}", "avg_launch_ms": avg, "launches": n_mode,
+                     "flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
+                     "fused_launch_avg_ms": (ms_fused / n_fused) if n_fused else None})
         out[prec] = {"value": w.N * steps / dt, "ms_per_step": 1e3 * dt / steps, "steps": steps,
-                     "rel_inf_err_vs_f64_gpu": err}
+                     "rel_inf_err_vs_f64_gpu": err, "roofline": roof}
         del solver, Ud, Vd, Ud2, Vd2
     return out
 

@@ -539,7 +539,10 @@ hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* co
     for (int g = 0; g < group; ++g)
       vec = vec && (reinterpret_cast<uintptr_t>(W[g]) % 16 == 0) &&
             (reinterpret_cast<uintptr_t>(Mf32[g]) % 16 == 0);
-    if (n <= 64) {
+    // 64-row tiles where 128-row ones would be ragged (n <= 64, or a multiple of
+    // 64 but not of 128)
+    const bool rows64 = n <= 64 || (n % 128 != 0 && n % 64 == 0);
+    if (rows64) {
       if (vec)
         return out_f64 ? launch_tiles(k_tgemm_f32<64, 128, true, true>, a, 64, 128, s)
                        : launch_tiles(k_tgemm_f32<64, 128, false, true>, a, 64, 128, s);
@@ -558,7 +561,7 @@ hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* co
     aligned = aligned && (reinterpret_cast<uintptr_t>(W[g]) % 16 == 0) &&
               (reinterpret_cast<uintptr_t>(Mh[g]) % 16 == 0) &&
               (reinterpret_cast<uintptr_t>(Ml[g]) % 16 == 0);
-  if (n <= 64) {
+  if (n <= 64 || (n % 128 != 0 && n % 64 == 0)) {
     const bool full = aligned && n % 64 == 0 && X % 128 == 0;
     if (full)
       return out_f64 ? launch_tiles(k_tgemm_bf16x3<64, 128, true, true>, a, 64, 128, s)

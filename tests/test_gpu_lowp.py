@@ -25,6 +25,8 @@ CASES = [
     ("fhn3d_48_50", S.fhn_3d(48, 50), 50),
     ("schnak2d_130x70_20", S.with_shape(S.schnakenberg_2d(), (130, 70)), 20),
     ("bruss1d_300_50", S.with_shape(S.brusselator_3d(), (300,)), 50),
+    # n = 192: 64-row tiles
+    ("bruss3d_192x64x40_10", S.with_shape(S.brusselator_3d(), (192, 64, 40)), 10),
 ]
 
 
