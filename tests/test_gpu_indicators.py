@@ -54,7 +54,10 @@ def test_indicators_count_nonfinite(dev):
     (S.with_shape(S.schnakenberg_2d(), (96, 80)), 12, 3),
     (S.with_shape(S.fhn_3d(), (24, 20, 28)), 10, 4),
     (S.with_shape(S.dib_2d(), (64, 64)), 6, 1),
-], ids=["schnak2d", "fhn3d", "dib2d"])
+    # evenly tiled: stage 2 runs in the epilogue of the last phi_1 product
+    (S.with_shape(S.schnakenberg_2d(), (128, 256)), 8, 2),
+    (S.with_shape(S.brusselator_3d(), (64, 32, 128)), 4, 2),
+], ids=["schnak2d", "fhn3d", "dib2d", "schnak2d_fused", "bruss3d_fused"])
 def test_solve_monitored_matches_oracle(dev, w, steps, every):
     p = O.problem_from_workload(w)
     mats = O.precompute(p)
