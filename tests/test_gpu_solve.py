@@ -158,3 +158,15 @@ def test_zero_steps_leaves_state(dev):
     U0, V0 = S.initial_state(w, 0)
     U, V = _gpu(dev, w, U0, V0, 0)
     assert np.array_equal(U, U0) and np.array_equal(V, V0)
+
+
+@pytest.mark.parametrize("shape", [(4096,), (4096, 24), (24, 4096)], ids=["1d", "2d_long_x1", "2d_long_x2"])
+def test_largest_direction_steady_state(dev, shape):
+    # n_mu = 4096, the largest size the boundary accepts: operators and matrix
+    # functions built on the device, 10 steps from the homogeneous equilibrium
+    # (1, 3) of the Brusselator stay there to rounding
+    w = S.with_shape(S.brusselator_3d(), shape)
+    U0 = np.full(w.n, w.base[0], order="F")
+    V0 = np.full(w.n, w.base[1], order="F")
+    U, V = _gpu(dev, w, U0, V0, 10)
+    assert np.abs(U - w.base[0]).max() <= 1e-11 and np.abs(V - w.base[1]).max() <= 1e-11
