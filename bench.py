@@ -265,8 +265,8 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only (the hot path is a single-GPU "
-              "kernel; sharding across GPUs is a design note, not implemented). Use --gpus 1.",
+        print("bench.py: measures one GPU only (the hot path is a single-GPU kernel; "
+              "sharding across GPUs is a design note, not implemented). Use --gpus 1.",
               file=sys.stderr)
         return 2
 

@@ -48,5 +48,5 @@ def adr():
 def dev(adr):
     """The GPU binding; fails (does not skip) when no GPU is visible."""
     import torch
-    assert torch.cuda.is_available(), "GPU tests need an MI355X (run them with -m gpu on the GPU box)"
+    assert torch.cuda.is_available(), "GPU tests need an MI355X (select them with -m gpu)"
     return adr
