@@ -15,7 +15,8 @@ the host's cores on a bounded sample of the same workload.
     python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--precision f64]
 
 Besides the main line's workload it reports (unless --no-extras): the FP32
-and split-BF16 products on the same grid, the 64-instance batched 2D
+and split-BF16 products on the same grid, the 2D Schnakenberg 64^2 and 3D
+FitzHugh-Nagumo 128^3 workloads, the 64-instance batched 2D
 Schnakenberg workload (grouped plans vs one-by-one), and the serving stream's
 p50/p99 latency and throughput (continuous batching vs the plain FP64 path
 one request at a time).
@@ -170,6 +171,58 @@ def _lowp_legs(adr, S, torch, w, steps, seed, ref_state):
         out[prec] = {"value": w.N * steps / dt, "ms_per_step": 1e3 * dt / steps, "steps": steps,
                      "rel_inf_err_vs_f64_gpu": err, "roofline": roof}
         del solver, Ud, Vd, Ud2, Vd2
+    return out
+
+
+def _workload_legs(adr, S, torch, seed):
+    """The other two model workloads at one GPU, FP64: the 2D Schnakenberg 64^2
+    (launch-bound at 4096 points) and the 3D FitzHugh-Nagumo 128^3, with the mode
+    products' position against the FP64 matrix peak.  The 64^2 problem is also
+    stepped as a one-problem grouped plan replayed from a HIP graph."""
+    out = {}
+    for name, w, steps in (("schnakenberg2d_64", S.schnakenberg_2d(64, 400), 400),
+                           ("fhn3d_128", S.fhn_3d(128, 200), 200)):
+        solver = adr.Solver(w)
+        U0, V0 = S.initial_state(w, seed)
+        Ud, Vd = solver.upload(U0, V0)
+        solver.solve(Ud, Vd, 3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solver.solve(Ud, Vd, steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        d = len(w.n)
+        adr.adr_timing_enable(steps * (2 * d + 4) + 8)
+        solver.solve(Ud, Vd, steps)
+        torch.cuda.synchronize()
+        n_mode, ms_mode = adr.adr_timing_read(0)
+        n_fused, ms_fused = adr.adr_timing_read(3)
+        n_all, ms_all = adr.adr_timing_read(2)
+        adr.adr_timing_enable(0)
+        # mode-product flops of a step: 4 Tucker operators, 2 components, 2 n_mu N each
+        flops_step = 8.0 * sum(w.n) * w.N
+        ms_products = ms_mode + ms_fused
+        tf = flops_step * steps / (ms_products * 1e-3) / 1e12 if ms_products > 0 else None
+        leg = {"grid": list(w.n), "steps": steps, "value": w.N * steps / dt,
+               "ms_per_step": 1e3 * dt / steps,
+               "mode_products": {"launches_per_step": (n_mode + n_fused) / steps,
+                                 "ms_per_step": ms_products / steps,
+                                 "tflops": tf, "peak": PEAKS["f64_mfma_tflops"],
+                                 "frac": tf / PEAKS["f64_mfma_tflops"] if tf else None},
+               "kernel_ms_per_step": ms_all / steps}
+        if name == "schnakenberg2d_64":
+            Ub, Vb = solver.upload(U0, V0)
+            b = adr.Batch([solver], [(Ub, Vb)], adr.ADR_BATCH_GRAPH)
+            b.run(3)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.run(steps)
+            torch.cuda.synchronize()
+            dtg = time.perf_counter() - t0
+            b.close()
+            leg["graph_plan"] = {"value": w.N * steps / dtg, "ms_per_step": 1e3 * dtg / steps}
+        out[name] = leg
+        del solver, Ud, Vd
     return out
 
 
@@ -334,6 +387,8 @@ def main(argv=None):
         torch.cuda.empty_cache()
         extras = {"precisions": _lowp_legs(adr, S, torch, w, args.lowp_steps, args.seed, ref)}
         del ref
+        torch.cuda.empty_cache()
+        extras["workloads"] = _workload_legs(adr, S, torch, args.seed)
         torch.cuda.empty_cache()
         extras["batched"] = _batched_leg(adr, S, torch, args.batch_steps, args.seed)
         torch.cuda.empty_cache()
