@@ -250,11 +250,23 @@ hipError_t time_phase(const adr_batch& b, const ModePhase& m, hipStream_t s, flo
   return e;
 }
 
+// Without autotuning: 128x128 tiles when the phase has work for several of them
+// per CU, else 64x64 (four times the tiles, and four workgroups per CU), which
+// the tuner picks for mixes of grids up to 512^2.
 TileCfg default_cfg(const adr_batch& b, int mu) {
-  int nmax = 0;
-  for (int i = 0; i < b.count; ++i)
-    if (mu < b.geoms[i].d) nmax = std::max(nmax, b.geoms[i].n[mu]);
-  return nmax <= 64 ? TileCfg::I64X128 : TileCfg::I128X128;
+  long long tiles128 = 0;
+  for (int i = 0; i < b.count; ++i) {
+    const Geometry& g = b.geoms[i];
+    if (mu >= g.d) continue;
+    const long long X = g.N / g.n[mu];
+    tiles128 += 2LL * ((g.n[mu] + 127) / 128) * ((X + 127) / 128);
+  }
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
+  return tiles128 >= 8LL * cus ? TileCfg::I128X128 : TileCfg::I64X64;
 }
 
 void destroy(adr_batch* b) {
