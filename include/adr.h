@@ -100,9 +100,12 @@ int adr_build_1d_ops(int n, double a, double b, double diff, double vel, int bc,
  *   A_dev            device, n*n doubles, column-major
  *   E_dev, P1_dev, P2_dev  device, n*n doubles each; any may be NULL (not computed)
  *   n                1 <= n <= 4096
- * Allocates a temporary device workspace of 10*n*n doubles and synchronises
- * `stream` once (to read back ||tau A||_1 and pick s).  Errors: ADR_EINVAL,
- * ADR_ENOMEM, ADR_EDEVICE, ADR_ENONFINITE (tau*A has a non-finite entry).
+ * Works in a per-device scratch of 14*n*n doubles that the library keeps
+ * between calls (allocated, or grown, when a larger n first arrives).  Calls
+ * are serialised by a lock; each synchronises `stream` twice (to read back
+ * ||tau A||_1 and pick s, and before returning, so the scratch is free for
+ * the next call).  Errors: ADR_EINVAL, ADR_ENOMEM, ADR_EDEVICE,
+ * ADR_ENONFINITE (tau*A has a non-finite entry).
  */
 int adr_precompute_phi(int n, const double* A_dev, double tau, double* E_dev,
                        double* P1_dev, double* P2_dev, void* stream);
