@@ -266,7 +266,7 @@ int adr_solve_monitored(const adr_problem* p, double* U, double* V, int nsteps, 
  */
 typedef struct adr_batch adr_batch;
 enum adr_batch_flags { ADR_BATCH_AUTOTUNE = 1, ADR_BATCH_GRAPH = 2, ADR_BATCH_PREPARED = 4 };
-/* ADR_BATCH_TILE(cfg): use tile configuration cfg (0..3, see adr_batch_info) for
+/* ADR_BATCH_TILE(cfg): use tile configuration cfg (0..4, see adr_batch_info) for
  * every FP64 mode-product phase instead of the default or the tuner's choice. */
 #define ADR_BATCH_TILE(cfg) (((cfg) + 1) << 8)
 int adr_batch_create(int count, const adr_problem* problems, double* const* U,
@@ -277,7 +277,8 @@ int adr_batch_run(adr_batch* plan, int nsteps, void* stream);
 /*
  * adr_batch_info -- the tile configuration chosen for the mode products of
  * each direction mu < max_phases (0: 64x64, 1: 64x128, 2: 128x64, 3: 128x128
- * rows x fibres; -1 where the plan has no FP64 phase), and whether a graph was
+ * rows x fibres, one tile per workgroup; 4: 64x64 tiles walked by persistent
+ * workgroups; -1 where the plan has no FP64 phase), and whether a graph was
  * captured.  Either output may be NULL when not wanted (tile_cfg only with
  * max_phases == 0).
  */

@@ -60,9 +60,10 @@ struct TileJob {
   long long tile_begin;   // first tile of this job in the grouped launch
 };
 
-// Tile configurations of the FP64 product (rows BI of M x fibres BX per workgroup).
-enum class TileCfg : int { I64X64 = 0, I64X128 = 1, I128X64 = 2, I128X128 = 3 };
-constexpr int kNumTileCfgs = 4;
+// Tile configurations of the FP64 product (rows BI of M x fibres BX per workgroup);
+// P64X64: 64x64 tiles walked by persistent workgroups (four per CU).
+enum class TileCfg : int { I64X64 = 0, I64X128 = 1, I128X64 = 2, I128X128 = 3, P64X64 = 4 };
+constexpr int kNumTileCfgs = 5;
 void tile_cfg_dims(TileCfg c, int& BI, int& BX);
 // Grouped FP64 products; `jobs` is a device array of `njobs` TileJobs whose tile
 // offsets were laid out for configuration `cfg`; `ntiles` is the total.

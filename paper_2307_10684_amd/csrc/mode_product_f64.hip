@@ -278,6 +278,219 @@ __global__ __launch_bounds__(64 * WI * WX, 2) void k_mode_f64_grouped(const Tile
   mode_tile_f64<BI, BX, WI, WX, BK, KFAST, false>(job, itile, xtile, sM, sW);
 }
 
+// Persistent grouped products: about MINB workgroups per CU walk the grouped tile
+// sequence (jobs sorted by tile offset) in rounds of one tile each, with the
+// first k-chunk of the next tile -- possibly of another job, with its own shape
+// -- loaded while the last chunk of the current tile is multiplied.  Loads and
+// stores are bounds-checked as in mode_tile_f64 (any shape), and every output
+// element is summed in the same order as there.
+template <int BI, int BX, int WI, int WX, int BK, bool KFAST, int MINB>
+__global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64_grouped_persist(
+    const TileJob* __restrict__ jobs, int njobs, long long ntiles) {
+  constexpr int NT = 64 * WI * WX;
+  constexpr int TI = BI / WI, TX = BX / WX;
+  constexpr int FI = TI / 16, FX = TX / 16;
+  static_assert(FI * 16 == TI && FX * 16 == TX, "wave tile must be a multiple of 16");
+  constexpr int LDI = BI + kPad;
+  constexpr int LDX = BX + kPad;
+  constexpr int LDK = BK + 2;
+  constexpr int SW = KFAST ? BX * LDK : BK * LDX;
+  constexpr int SM = BK * LDI;
+  constexpr int MROWS = NT / BI;
+  constexpr int MLOADS = BK / MROWS;
+  static_assert(MROWS * BI == NT && MLOADS * MROWS == BK, "M tile mapping");
+  constexpr int WROWS = NT / BX;
+  constexpr int XSTEP = NT / BK;
+  constexpr int WLOADS = BX * BK / NT;
+  static_assert(KFAST ? (XSTEP * BK == NT && WLOADS * XSTEP == BX)
+                      : (WROWS * BX == NT && WLOADS * WROWS == BK), "W tile mapping");
+  __shared__ double sM[2 * SM];
+  __shared__ double sW[2 * SW];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wi = wave / WX, wx = wave % WX;
+  const int col = lane & 15;
+  const int krow = lane >> 4;
+
+  // round k: the grid takes tiles [k*G, (k+1)*G), dealt as the one-tile-per-
+  // workgroup launch deals them (xcd_tile), so every workgroup sees the same mix
+  // of long and short contractions
+  const long long G = gridDim.x;
+  const long long b = blockIdx.x;
+  const long long off = xcd_tile(b, G);
+  auto tile_index = [&](long long k) -> long long {
+    const long long t = k * G + off;
+    return t < ntiles ? t : -1;
+  };
+
+  // per-tile state: the job's geometry and this thread's load descriptors
+  struct Tile {
+    TileJob job;
+    int i0;
+    unsigned x0, L, X, Ln;
+    bool m_iok, w_ok;
+    unsigned m_base, w_base;
+  };
+  const int m_i = tid % BI, m_k0 = tid / BI;
+  const int w_a = KFAST ? tid % BK : tid % BX;
+  const int w_b = KFAST ? tid / BK : tid / BX;
+  auto tile_of = [&](long long t) {
+    Tile d;
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (jobs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+    }
+    d.job = jobs[lo];
+    const long long local = t - d.job.tile_begin;
+    d.i0 = (int)(local % d.job.n_itiles) * BI;
+    d.x0 = (unsigned)(local / d.job.n_itiles) * BX;
+    d.L = (unsigned)d.job.L;
+    d.X = (unsigned)d.job.X;
+    d.Ln = d.L * (unsigned)d.job.n;
+    d.m_iok = (d.i0 + m_i) < d.job.n;
+    d.m_base = (unsigned)(d.i0 + m_i) + (unsigned)d.job.n * (unsigned)m_k0;
+    if (!KFAST) {
+      const unsigned x = d.x0 + w_a;
+      d.w_ok = x < d.X;
+      d.w_base = d.w_ok ? (x % d.L) + d.Ln * (x / d.L) + d.L * (unsigned)w_b : 0u;
+    } else {
+      d.w_ok = true;
+      d.w_base = (d.x0 + w_b) * (unsigned)d.job.n + (unsigned)w_a;
+    }
+    return d;
+  };
+
+  double rm[MLOADS], rw[WLOADS];
+  auto m_ok = [&](const Tile& d, int k0, int p) {
+    return d.m_iok && (k0 + m_k0 + p * MROWS) < d.job.n;
+  };
+  auto w_okp = [&](const Tile& d, int k0, int p) {
+    return KFAST ? ((k0 + w_a) < d.job.n && (d.x0 + w_b + p * XSTEP) < d.X)
+                 : (d.w_ok && (k0 + w_b + p * WROWS) < d.job.n);
+  };
+  auto load_chunk = [&](const Tile& d, int k0) {
+    const unsigned n = (unsigned)d.job.n;
+#pragma unroll
+    for (int p = 0; p < MLOADS; ++p)
+      rm[p] = d.job.M[m_ok(d, k0, p) ? d.m_base + n * (unsigned)(k0 + p * MROWS) : 0u];
+#pragma unroll
+    for (int p = 0; p < WLOADS; ++p) {
+      const unsigned off = KFAST ? n * (unsigned)(p * XSTEP) + (unsigned)k0
+                                 : d.L * (unsigned)(k0 + p * WROWS);
+      rw[p] = d.job.W[w_okp(d, k0, p) ? d.w_base + off : 0u];
+    }
+  };
+  auto store_chunk = [&](const Tile& d, int buf, int k0) {
+#pragma unroll
+    for (int p = 0; p < MLOADS; ++p)
+      sM[buf * SM + (m_k0 + p * MROWS) * LDI + m_i] = m_ok(d, k0, p) ? rm[p] : 0.0;
+#pragma unroll
+    for (int p = 0; p < WLOADS; ++p) {
+      const double v = w_okp(d, k0, p) ? rw[p] : 0.0;
+      if (!KFAST)
+        sW[buf * SW + (w_b + p * WROWS) * LDX + w_a] = v;
+      else
+        sW[buf * SW + (w_b + p * XSTEP) * LDK + w_a] = v;
+    }
+  };
+
+  long long k = 0;
+  const long long t0 = tile_index(0);
+  if (t0 < 0) return;
+  Tile cur = tile_of(t0);
+  load_chunk(cur, 0);
+  store_chunk(cur, 0, 0);
+  __syncthreads();
+  int buf = 0;
+  while (true) {
+    const long long tn = tile_index(k + 1);
+    const Tile nxt = tile_of(tn < 0 ? t0 : tn);
+    d4 acc[FI][FX];
+#pragma unroll
+    for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+      for (int fx = 0; fx < FX; ++fx) acc[fi][fx] = d4{0.0, 0.0, 0.0, 0.0};
+    const int nchunks = (cur.job.n + BK - 1) / BK;
+    for (int c = 0; c < nchunks; ++c) {
+      const bool in_tile = c + 1 < nchunks;
+      const bool more = in_tile || tn >= 0;
+      if (more) load_chunk(in_tile ? cur : nxt, in_tile ? (c + 1) * BK : 0);
+      const double* sm = sM + buf * SM;
+      const double* sw = sW + buf * SW;
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        const int kr = kk + krow;
+        double af[FI], bf[FX];
+#pragma unroll
+        for (int fi = 0; fi < FI; ++fi) af[fi] = sm[kr * LDI + wi * TI + fi * 16 + col];
+#pragma unroll
+        for (int fx = 0; fx < FX; ++fx) {
+          const int xl = wx * TX + fx * 16 + col;
+          bf[fx] = KFAST ? sw[xl * LDK + kr] : sw[kr * LDX + xl];
+        }
+#pragma unroll
+        for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+          for (int fx = 0; fx < FX; ++fx)
+            acc[fi][fx] = KFAST ? __builtin_amdgcn_mfma_f64_16x16x4f64(bf[fx], af[fi], acc[fi][fx], 0, 0, 0)
+                                : __builtin_amdgcn_mfma_f64_16x16x4f64(af[fi], bf[fx], acc[fi][fx], 0, 0, 0);
+      }
+      if (more) store_chunk(in_tile ? cur : nxt, buf ^ 1, in_tile ? (c + 1) * BK : 0);
+      __syncthreads();
+      buf ^= 1;
+    }
+    // epilogue (as mode_tile_f64): out = alpha*acc + beta*Y + gamma*Z
+    const TileJob& j = cur.job;
+    const int n = j.n;
+    if (!KFAST) {
+#pragma unroll
+      for (int fx = 0; fx < FX; ++fx) {
+        const unsigned x = cur.x0 + wx * TX + fx * 16 + col;
+        if (x >= cur.X) continue;
+        const unsigned xo = (x % cur.L) + cur.Ln * (x / cur.L);
+#pragma unroll
+        for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = cur.i0 + wi * TI + fi * 16 + krow + 4 * v;
+            if (i < n) {
+              const unsigned o = xo + cur.L * (unsigned)i;
+              double val = j.alpha * acc[fi][fx][v];
+              if (j.Y) val += j.beta * j.Y[o];
+              if (j.Z) val += j.gamma * j.Z[o];
+              j.out[o] = val;
+            }
+          }
+      }
+    } else {
+#pragma unroll
+      for (int fi = 0; fi < FI; ++fi) {
+        const int i = cur.i0 + wi * TI + fi * 16 + col;
+        if (i >= n) continue;
+#pragma unroll
+        for (int fx = 0; fx < FX; ++fx)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const unsigned x = cur.x0 + wx * TX + fx * 16 + krow + 4 * v;
+            if (x < cur.X) {
+              const unsigned o = x * (unsigned)n + (unsigned)i;
+              double val = j.alpha * acc[fi][fx][v];
+              if (j.Y) val += j.beta * j.Y[o];
+              if (j.Z) val += j.gamma * j.Z[o];
+              j.out[o] = val;
+            }
+          }
+      }
+    }
+    if (tn < 0) break;
+    cur = nxt;
+    ++k;
+  }
+}
+
 // Epilogue of a V tile that carries ETD2RKds stage 2 (see k_mode_f64_persist),
 // for reaction model MODEL.  The six tensors are distinct buffers: the
 // restrict-qualified parameters let the loads of a batch of elements be issued
@@ -713,7 +926,8 @@ hipError_t launch_grouped(bool kfast, const TileJob* jobs, int njobs, long long 
 
 void tile_cfg_dims(TileCfg c, int& BI, int& BX) {
   switch (c) {
-    case TileCfg::I64X64: BI = 64; BX = 64; break;
+    case TileCfg::I64X64:
+    case TileCfg::P64X64: BI = 64; BX = 64; break;
     case TileCfg::I64X128: BI = 64; BX = 128; break;
     case TileCfg::I128X64: BI = 128; BX = 64; break;
     default: BI = 128; BX = 128; break;
@@ -726,6 +940,18 @@ hipError_t launch_mode_grouped_f64(TileCfg cfg, bool kfast, const TileJob* jobs,
     case TileCfg::I64X64: return launch_grouped<64, 64, 2, 2>(kfast, jobs, njobs, ntiles, s);
     case TileCfg::I64X128: return launch_grouped<64, 128, 1, 4>(kfast, jobs, njobs, ntiles, s);
     case TileCfg::I128X64: return launch_grouped<128, 64, 2, 2>(kfast, jobs, njobs, ntiles, s);
+    case TileCfg::P64X64: {
+      if (njobs <= 0 || ntiles <= 0 || ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
+      long long grid = 4LL * device_cu_count();
+      if (grid > ntiles) grid = ntiles;
+      if (kfast)
+        hipLaunchKernelGGL((k_mode_f64_grouped_persist<64, 64, 2, 2, 16, true, 4>), dim3((unsigned)grid),
+                           dim3(256), 0, s, jobs, njobs, ntiles);
+      else
+        hipLaunchKernelGGL((k_mode_f64_grouped_persist<64, 64, 2, 2, 16, false, 4>), dim3((unsigned)grid),
+                           dim3(256), 0, s, jobs, njobs, ntiles);
+      return hipGetLastError();
+    }
     default: return launch_grouped<128, 128, 2, 2>(kfast, jobs, njobs, ntiles, s);
   }
 }

@@ -172,7 +172,7 @@ def test_batch_create_validates_before_device_work(adr):
     ok = _problem(adr)
     assert _batch_create(adr, []) == adr.ADR_EINVAL
     assert _batch_create(adr, [ok], flags=8) == adr.ADR_EINVAL
-    assert _batch_create(adr, [ok], flags=adr.ADR_BATCH_TILE(4)) == adr.ADR_EINVAL
+    assert _batch_create(adr, [ok], flags=adr.ADR_BATCH_TILE(5)) == adr.ADR_EINVAL
     assert _batch_create(adr, [ok], U=None) == adr.ADR_EINVAL
     assert _batch_create(adr, [ok], work=4097) == adr.ADR_EINVAL
     assert _batch_create(adr, [ok, ok], work_bytes=64) == adr.ADR_ENOMEM
