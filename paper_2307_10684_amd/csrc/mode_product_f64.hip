@@ -962,33 +962,71 @@ bool mode_f64_stage2_fusable(const ModeArgs& a) {
   return a.n % 128 != 0 ? persist_fits<64, 128, 16>(a) : persist_fits<128, 128, 16>(a);
 }
 
+// Whether `units` work items, dealt to `slots` persistent workgroups in
+// contiguous ranges, keep them busy: at least one whole round, and the last
+// round at least a quarter full (at 256^3: 2048 tiles of 128x128 for 512 slots).
+static bool fills_rounds(long long units, long long slots) {
+  if (units < slots) return false;
+  const long long rounds = (units + slots - 1) / slots;
+  return 4 * units >= 3 * rounds * slots;
+}
+
+// Workgroups that receive work when `units` are dealt in ranges of ceil(units / slots).
+static long long active_workgroups(long long units, long long slots) {
+  const long long per = (units + slots - 1) / slots;
+  return (units + per - 1) / per;
+}
+
 hipError_t launch_mode_product_f64(const ModeArgs& a, hipStream_t s) {
   hipError_t e = hipSuccess;
+  const long long slots = 2LL * device_cu_count();   // persistent grid (two workgroups per CU)
   if (a.Rout[0] || a.Rout[1]) {
-    // stage 2 in the epilogue: only the persistent x-contiguous kernels carry it
+    // stage 2 in the epilogue: only the persistent x-contiguous kernels carry it.
+    // A workgroup takes U/V tile pairs; of the tile shapes that fit, the largest
+    // one that puts the most workgroups to work (measured: 128^3 47 us with
+    // 64x64 tiles against 72 with 128x128, 1024^2 184 against 319, 256^3 keeps
+    // 128x128).
     if (!a.Rout[0] || !a.Rout[1] || !mode_f64_stage2_fusable(a)) return hipErrorInvalidValue;
-    if (a.n % 128 != 0) launch_persist<64, 128, 1, 4, 16>(a, s, e);
-    else launch_persist<128, 128, 2, 2, 16>(a, s, e);
-    return e;
+    const long long u128 = persist_fits<128, 128, 16>(a) ? (a.n / 128) * (a.X / 128) : 0;
+    const long long u64x128 = persist_fits<64, 128, 16>(a) ? (a.n / 64) * (a.X / 128) : 0;
+    const long long u64 = persist_fits<64, 64, 16>(a) ? (a.n / 64) * (a.X / 64) : 0;
+    long long best = 0;
+    int pick = 0;
+    if (u128 && active_workgroups(u128, slots) > best) { best = active_workgroups(u128, slots); pick = 1; }
+    if (u64x128 && active_workgroups(u64x128, slots) > best) { best = active_workgroups(u64x128, slots); pick = 2; }
+    if (u64 && active_workgroups(u64, slots) > best) pick = 3;
+    bool launched = false;
+    if (pick == 1) launched = launch_persist<128, 128, 2, 2, 16>(a, s, e);
+    else if (pick == 2) launched = launch_persist<64, 128, 1, 4, 16>(a, s, e);
+    else if (pick == 3) launched = launch_persist<64, 64, 2, 2, 16>(a, s, e);
+    return launched ? e : hipErrorInvalidValue;
   }
   // short contractions (n < 128): 64x64 tiles, one per workgroup, four
   // workgroups per CU (measured at 64^3: 8 us per direction against 10-19 with
   // 64-row persistent tiles; 80^3: 13 against 22)
   if (a.n < 128) return launch_cfg<64, 64, 2, 2, 16, 4>(a, s);
-  // 64-row persistent tiles where 128-row ones would be ragged (n % 128 != 0,
-  // n % 64 == 0): at 192^3 they run at 39 TFLOP/s against 30 for ragged
-  // one-tile-per-workgroup 128-row tiles (measured)
-  if (a.n % 128 != 0 && launch_persist<64, 128, 1, 4, 16>(a, s, e)) return e;
+  // 128x128 persistent tiles where they fill whole rounds of the grid;
   // fibre-contiguous products (L = 1) run best with a 2 x 4 wave grid (64 x 32
   // per wave), the others with 2 x 2 (64 x 64 per wave), measured at 256^3
-  if (a.L == 1 && launch_persist<128, 128, 2, 4, 16>(a, s, e)) return e;
-  if (a.L != 1 && launch_persist<128, 128, 2, 2, 16>(a, s, e)) return e;
-  // strided products whose L is a multiple of 64 but not of 128 (a tile's
-  // fibres must stay within one batch): 64-wide persistent tiles (192^3,
-  // mu = 2: 41 TFLOP/s against 30)
-  if (a.L != 1 && a.L % 64 == 0) {
-    if (a.n % 128 == 0 && launch_persist<128, 64, 2, 2, 16>(a, s, e)) return e;
-    if (launch_persist<64, 64, 2, 2, 16>(a, s, e)) return e;
+  if (persist_fits<128, 128, 16>(a) &&
+      fills_rounds((long long)a.group * (a.n / 128) * (a.X / 128), slots)) {
+    if (a.L == 1 && launch_persist<128, 128, 2, 4, 16>(a, s, e)) return e;
+    if (a.L != 1 && launch_persist<128, 128, 2, 2, 16>(a, s, e)) return e;
+  }
+  // long contractions that 128-row tiles would leave ragged (n % 128 != 0):
+  // 64x128 persistent tiles (320x192x64, mu = 1: 111 us against 116 for 64x64)
+  if (a.n % 128 != 0 && a.n >= 256 && persist_fits<64, 128, 16>(a) &&
+      fills_rounds((long long)a.group * (a.n / 64) * (a.X / 128), slots) &&
+      launch_persist<64, 128, 1, 4, 16>(a, s, e))
+    return e;
+  // otherwise 64x64 tiles: persistent when they fit in one round, else one per
+  // workgroup at four workgroups per CU (measured: 192^3 128 us against 140 for
+  // 64x128 tiles; 192x192x128, mu = 3: 59 against 91 for 128x128; 1024^2 93
+  // against 152; 1536^2 324 against 405)
+  if (persist_fits<64, 64, 16>(a)) {
+    if ((long long)a.group * (a.n / 64) * (a.X / 64) <= slots && launch_persist<64, 64, 2, 2, 16>(a, s, e))
+      return e;
+    return launch_cfg<64, 64, 2, 2, 16, 4>(a, s);
   }
   // ragged shapes: 64-row tiles waste fewer rows while n is short
   if (a.n < 256) return launch_cfg<64, 64, 2, 2, 16, 4>(a, s);

@@ -22,8 +22,10 @@ SHAPES = [
     (7,), (64,), (300,),
     (64, 64), (33, 70), (130, 48), (256, 17), (5, 129),
     (16, 24, 40), (72, 40, 150), (64, 64, 64), (31, 17, 3), (3, 200, 9),
-    # 64-row, 128x64 and 64x64 persistent tiles; the largest n the boundary accepts
+    # 64-row and 64x64 tiles; the largest n the boundary accepts
     (192, 128, 64), (64, 192, 48), (320, 192, 16), (4096, 24), (24, 4096),
+    # few 128x128 tiles for the chip: 64x64 tiles, persistent or one per workgroup
+    (384, 640), (128, 128, 128),
 ]
 
 

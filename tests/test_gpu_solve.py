@@ -65,14 +65,16 @@ CASES = [
     ("dib2d_96x80_40", S.with_shape(S.dib_2d(200, 1250), (96, 80)), 40),
     ("paper_schnak3d_80_10", S.paper_schnakenberg_3d(80, 50), 10),
     # evenly tiled grids: the last product of the phi_1 operator also computes
-    # stage 2 (128-row tiles; 64-row tiles for n_d = 64)
+    # stage 2 (64x64 persistent tiles at these sizes, 128x128 at 256^3)
     ("schnakenberg2d_256x128_20", S.with_shape(S.schnakenberg_2d(), (256, 128)), 20),
     ("bruss3d_64x128x64_10", S.with_shape(S.brusselator_3d(), (64, 128, 64)), 10),
     ("dib2d_128x256_10", S.with_shape(S.dib_2d(200, 1250), (128, 256)), 10),
-    # n % 64 == 0 but not % 128: 64-row persistent tiles (and stage 2 on them)
+    # n % 64 == 0 but not % 128: 64-row tiles for the products and stage 2
     ("schnakenberg2d_128x192_20", S.with_shape(S.schnakenberg_2d(), (128, 192)), 20),
+    # stage 2 carried by persistent 64x64 tiles (few tiles for the chip)
+    ("schnakenberg2d_384x384_3", S.with_shape(S.schnakenberg_2d(), (384, 384)), 3),
     ("fhn3d_192x128x64_5", S.with_shape(S.fhn_3d(), (192, 128, 64)), 5),
-    # strided direction with L % 128 != 0, L % 64 == 0: 64-wide persistent tiles
+    # strided direction with L % 128 != 0, L % 64 == 0: 64x64 tiles
     ("bruss3d_64x192x48_5", S.with_shape(S.brusselator_3d(), (64, 192, 48)), 5),
 ]
 
