@@ -499,6 +499,18 @@ __global__ __launch_bounds__(256) void k_split_bf16(int n, const double* __restr
   }
 }
 
+int lowp_cu_count() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+  }
+  return cus;
+}
+
 template <class K>
 hipError_t launch_tiles(K kern, const LowpArgs& a, int BI, int BX, hipStream_t s) {
   const int n_itiles = (a.n + BI - 1) / BI;
@@ -533,15 +545,18 @@ hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* co
   a.n = n;
   a.X = (unsigned)X;
   a.group = group;
+  // 64-row tiles where 128-row ones would be ragged (n <= 64, or a multiple of
+  // 64 but not of 128), or fewer than two per CU (measured, FP32 / split BF16:
+  // 1024^2 59 / 31 us against 94 / 39; 128^3 18 / 11 against 19 / 12; at 256^3,
+  // 2048 tiles, 128 rows stay ahead: 185 / 82 against 197 / 89)
+  const long long tiles128 = (long long)group * ((n + 127) / 128) * ((X + 127) / 128);
+  const bool rows64 = n <= 64 || (n % 128 != 0 && n % 64 == 0) || tiles128 < 2LL * lowp_cu_count();
   if (precision == 1) {
     // n % 4 == 0 with 16-byte aligned operands: four floats per lane per load
     bool vec = n % 4 == 0;
     for (int g = 0; g < group; ++g)
       vec = vec && (reinterpret_cast<uintptr_t>(W[g]) % 16 == 0) &&
             (reinterpret_cast<uintptr_t>(Mf32[g]) % 16 == 0);
-    // 64-row tiles where 128-row ones would be ragged (n <= 64, or a multiple of
-    // 64 but not of 128)
-    const bool rows64 = n <= 64 || (n % 128 != 0 && n % 64 == 0);
     if (rows64) {
       if (vec)
         return out_f64 ? launch_tiles(k_tgemm_f32<64, 128, true, true>, a, 64, 128, s)
@@ -561,7 +576,7 @@ hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* co
     aligned = aligned && (reinterpret_cast<uintptr_t>(W[g]) % 16 == 0) &&
               (reinterpret_cast<uintptr_t>(Mh[g]) % 16 == 0) &&
               (reinterpret_cast<uintptr_t>(Ml[g]) % 16 == 0);
-  if (n <= 64 || (n % 128 != 0 && n % 64 == 0)) {
+  if (rows64) {
     const bool full = aligned && n % 64 == 0 && X % 128 == 0;
     if (full)
       return out_f64 ? launch_tiles(k_tgemm_bf16x3<64, 128, true, true>, a, 64, 128, s)

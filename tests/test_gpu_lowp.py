@@ -27,6 +27,8 @@ CASES = [
     ("bruss1d_300_50", S.with_shape(S.brusselator_3d(), (300,)), 50),
     # n = 192: 64-row tiles
     ("bruss3d_192x64x40_10", S.with_shape(S.brusselator_3d(), (192, 64, 40)), 10),
+    # evenly tiled, fewer than two 128-row tiles per CU: 64-row tiles
+    ("schnak2d_512x384_5", S.with_shape(S.schnakenberg_2d(), (512, 384)), 5),
 ]
 
 
