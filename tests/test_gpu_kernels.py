@@ -26,6 +26,8 @@ SHAPES = [
     (192, 128, 64), (64, 192, 48), (320, 192, 16), (4096, 24), (24, 4096),
     # few 128x128 tiles for the chip: 64x64 tiles, persistent or one per workgroup
     (384, 640), (128, 128, 128),
+    # n = 320 (not a multiple of 128) with enough tiles: 64x128 persistent tiles
+    (320, 192, 64),
 ]
 
 

@@ -73,6 +73,9 @@ CASES = [
     ("schnakenberg2d_128x192_20", S.with_shape(S.schnakenberg_2d(), (128, 192)), 20),
     # stage 2 carried by persistent 64x64 tiles (few tiles for the chip)
     ("schnakenberg2d_384x384_3", S.with_shape(S.schnakenberg_2d(), (384, 384)), 3),
+    # stage 2 on 64x128 tiles (256 pairs of 128x128 tiles would leave half the
+    # persistent workgroups idle)
+    ("bruss3d_128x128x256_1", S.with_shape(S.brusselator_3d(), (128, 128, 256)), 1),
     ("fhn3d_192x128x64_5", S.with_shape(S.fhn_3d(), (192, 128, 64)), 5),
     # strided direction with L % 128 != 0, L % 64 == 0: 64x64 tiles
     ("bruss3d_64x192x48_5", S.with_shape(S.brusselator_3d(), (64, 192, 48)), 5),
