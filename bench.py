@@ -14,6 +14,9 @@ the host's cores on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps 100] [--warmup 5] [--precision f64]
 
+`--workload fhn3d` or `--workload schnakenberg2d` (with --no-extras) puts
+another model's workload on the main line, for profiling it alone.
+
 Besides the main line's workload it reports (unless --no-extras): the FP32
 and split-BF16 products on the same grid, the 2D Schnakenberg 64^2 and 3D
 FitzHugh-Nagumo 128^3 workloads, the 64-instance batched 2D
@@ -53,6 +56,15 @@ def _src_hash(name: str) -> str:
         lines = [ln.split("//", 1)[0].rstrip() for ln in f]
     code = "\n".join(ln for ln in lines if ln)
     return hashlib.sha256(code.encode()).hexdigest()[:16]
+
+
+# main workloads: synth builder, default grid side, model description
+WORKLOADS = {
+    "brusselator3d": ("brusselator_3d", 256,
+                      "advective Brusselator (A=1, B=3, Du=1e-3, Dv=5e-3, alpha=0.1*(1,.5,.25))"),
+    "fhn3d": ("fhn_3d", 128, "FitzHugh-Nagumo (delta=4, eps=0.1, a1=2, a0=0)"),
+    "schnakenberg2d": ("schnakenberg_2d", 64, "Schnakenberg (a=0.1, b=0.9, d=10, gamma=200)"),
+}
 
 
 def _traffic_from_profiles(precision: str, workload: str):
@@ -301,7 +313,11 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16x3"])
     ap.add_argument("--scheme", default="etd2rkds", choices=["etd2rkds", "lawson2b"])
-    ap.add_argument("--n", type=int, default=256, help="grid side of the 3D Brusselator workload")
+    ap.add_argument("--workload", default="brusselator3d", choices=sorted(WORKLOADS),
+                    help="main workload (the default is the benchmark's; the others are for profiling)")
+    ap.add_argument("--n", type=int, default=None,
+                    help="grid side of the main workload (default 256 / 128 / 64 for "
+                         "brusselator3d / fhn3d / schnakenberg2d)")
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--seed", type=int, default=0)
@@ -337,7 +353,8 @@ def main(argv=None):
         torch.cuda.synchronize()
         del src, dst
 
-    w = S.brusselator_3d(args.n)
+    builder, n_default, model_text = WORKLOADS[args.workload]
+    w = getattr(S, builder)(args.n or n_default)
     d, N = w.d, w.N
     solver = adr.Solver(w, scheme=args.scheme, precision=args.precision)
     U0, V0 = S.initial_state(w, args.seed)
@@ -444,7 +461,7 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": w.name, "grid": list(w.n), "scheme": args.scheme,
                    "precision": args.precision, "tau": w.tau, "seed": args.seed,
-                   "model": "advective Brusselator (A=1, B=3, Du=1e-3, Dv=5e-3, alpha=0.1*(1,.5,.25))"},
+                   "model": model_text},
         "roofline": {
             "kernel": f"mode_product_{args.precision}",
             "bound": "hbm" if hbm_bound else "mfma",
