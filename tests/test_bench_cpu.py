@@ -1,0 +1,70 @@
+"""Host-side checks of bench.py: the one-GPU contract, the workload table, the
+counter summaries it reads for its traffic figures, and the CPU-baseline
+record.  Nothing here touches a GPU."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+import bench
+import synth as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+@pytest.mark.parametrize("key", sorted(bench.WORKLOADS))
+def test_workload_table_builds_its_workloads(key):
+    builder, n, model = bench.WORKLOADS[key]
+    w = getattr(S, builder)(n)
+    assert w.name == f"{key}_{n}"
+    assert all(side == n for side in w.n)
+    assert model
+
+
+def test_default_workload_is_the_benchmark_grid():
+    builder, n, _ = bench.WORKLOADS["brusselator3d"]
+    w = getattr(S, builder)(n)
+    assert w.n == (256, 256, 256) and w.tau == 5e-3
+
+
+def test_source_hash_ignores_comments_and_blank_lines(tmp_path, monkeypatch):
+    csrc = tmp_path / "paper_2307_10684_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    (csrc / "k.hip").write_text("int a = 1;  // one\n\n// note\nint b = 2;\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h1 = bench._src_hash("k.hip")
+    (csrc / "k.hip").write_text("int a = 1;\n// another note\n\n\nint b = 2;  // two\n")
+    assert bench._src_hash("k.hip") == h1
+    (csrc / "k.hip").write_text("int a = 1;\nint b = 3;\n")
+    assert bench._src_hash("k.hip") != h1
+
+
+@pytest.mark.parametrize("precision,workload", [
+    ("f64", "brusselator3d_256"), ("f32", "brusselator3d_256"), ("bf16x3", "brusselator3d_256"),
+    ("f64", "fhn3d_128"), ("f64", "schnakenberg2d_64")])
+def test_committed_counter_summaries_match_the_kernel_sources(precision, workload):
+    # a summary taken before the kernel's code last changed is ignored by bench.py
+    # (traffic null); the committed ones must be current
+    traffic = bench._traffic_from_profiles(precision, workload)
+    assert traffic is not None and traffic > 0
+
+
+def test_committed_stage_summary_matches_the_kernel_source():
+    assert bench._stage_traffic_from_profiles("brusselator3d_256", True) is not None
+
+
+def test_cpu_baseline_record():
+    w = S.schnakenberg_2d(16, 2)
+    rec = bench.cpu_baseline(w, 2)
+    assert rec["kind"] == "oracle" and rec["unit"] == "grid-point-steps/s"
+    assert rec["value"] > 0 and rec["cores"] >= 1
+    assert "schnakenberg2d_16" in rec["sample"]
