@@ -46,6 +46,8 @@ PEAKS = {  # published MI355X dense peaks
 }
 MODE_SRC = {"f64": "mode_product_f64.hip", "f32": "mode_product_lowp.hip",
             "bf16x3": "mode_product_lowp.hip"}
+# BF16 MFMA products per FP32-equivalent product of a split-BF16 precision
+SPLIT_PRODUCTS = {"bf16x3": 3}
 
 
 def _src_hash(name: str) -> str:
@@ -109,40 +111,92 @@ def _stage_traffic_from_profiles(workload: str, stage1_only: bool):
         return None
 
 
-def cpu_baseline(workload, steps: int = 2):
-    """The oracle as it stands, timed on the host for a bounded number of steps."""
-    import numpy as np
-    import oracle as O
-    import synth as S
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:  # pragma: no cover
+        pass
+    return "unknown"
+
+
+def _blas_threads() -> int:
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        return max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
+        return os.cpu_count() or 1
+
+
+def oracle_sample(workload, seed: int, steps: int):
+    """The oracle's state after `steps` steps from the seeded initial state (the
+    reference the GPU runs are compared against), and the wall time of the last
+    steps - 1 of them (the first step is the warm-up)."""
+    import oracle as O
+    import synth as S
     p = O.problem_from_workload(workload)
     mats = O.precompute(p)
-    U, V = S.initial_state(workload, 0)
+    U, V = S.initial_state(workload, seed)
     U, V = O.etd2rkds_step(U, V, p, mats)  # first touch outside the timing
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for _ in range(steps - 1):
         U, V = O.etd2rkds_step(U, V, p, mats)
-    dt = time.perf_counter() - t0
-    return {
-        "value": workload.N * steps / dt,
+    return (U, V), time.perf_counter() - t0, (p, mats)
+
+
+def cpu_baseline(workload, seed: int, steps: int = 5, single_steps: int = 1):
+    """The oracle as it stands, timed on the host: `steps - 1` steps with the BLAS
+    library on all the threads it takes (the line's value), then `single_steps`
+    more on one thread.  Returns the record and the oracle state after `steps`
+    steps from the initial state."""
+    import oracle as O
+    threads = _blas_threads()
+    ref, dt, (p, mats) = oracle_sample(workload, seed, steps)
+    rec = {
+        "value": workload.N * (steps - 1) / dt,
         "unit": "grid-point-steps/s",
         "cores": int(threads),
         "kind": "oracle",
-        "sample": f"{steps} ETD2RKds steps of {workload.name} (numpy FP64 oracle, "
-                  f"{dt:.1f} s, BLAS threads={threads}, host cpus={os.cpu_count()})",
+        "cpu_model": _cpu_model(),
+        "host_cpus": os.cpu_count(),
+        "sample": f"{steps - 1} ETD2RKds steps of {workload.name} after one warm-up step "
+                  f"(numpy FP64 oracle, {dt:.1f} s, BLAS threads={threads})",
     }
+    if single_steps > 0:
+        try:
+            from threadpoolctl import threadpool_limits
+            U, V = ref
+            with threadpool_limits(limits=1):
+                t0 = time.perf_counter()
+                for _ in range(single_steps):
+                    U, V = O.etd2rkds_step(U, V, p, mats)
+                dt1 = time.perf_counter() - t0
+            rec["single_thread"] = {"value": workload.N * single_steps / dt1, "cores": 1,
+                                    "sample": f"{single_steps} ETD2RKds step(s) of {workload.name}, "
+                                              f"BLAS on one thread ({dt1:.1f} s)"}
+        except Exception as exc:  # pragma: no cover
+            rec["single_thread"] = {"error": repr(exc)}
+    return rec, ref
 
 
-def _lowp_legs(adr, S, torch, w, steps, seed, ref_state):
-    """Throughput of the reduced-precision products on the same workload, and the
-    difference from the FP64 GPU path after the same steps."""
-    out = {}
+def _rel_err(Ud, Vd, ref):
+    """max over components of ||gpu - oracle||_inf / ||oracle||_inf."""
     import numpy as np
-    for prec in ("f32", "bf16x3"):
+    Ur, Vr = ref
+    shape = Ur.shape
+    Ug = Ud.detach().cpu().numpy().reshape(shape, order="F")
+    Vg = Vd.detach().cpu().numpy().reshape(shape, order="F")
+    return max(float(np.abs(Ug - Ur).max() / np.abs(Ur).max()),
+               float(np.abs(Vg - Vr).max() / np.abs(Vr).max()))
+
+
+def _precision_legs(adr, S, torch, w, steps, seed, oracle_ref, precisions):
+    """Throughput of each precision's products on the same workload, and its
+    error against the FP64 oracle after the oracle sample's steps."""
+    out = {}
+    ref_steps, ref_state = oracle_ref if oracle_ref else (0, None)
+    for prec in precisions:
         solver = adr.Solver(w, precision=prec)
         U0, V0 = S.initial_state(w, seed)
         Ud, Vd = solver.upload(U0, V0)
@@ -155,47 +209,84 @@ def _lowp_legs(adr, S, torch, w, steps, seed, ref_state):
         dt = time.perf_counter() - t0
         err = None
         if ref_state is not None:
-            Ur, Vr = ref_state
-            err = max(float((Ud2 - Ur).abs().max() / Ur.abs().max()),
-                      float((Vd2 - Vr).abs().max() / Vr.abs().max()))
-        # a separate pass with HIP events around each launch: the products' roofline
-        d = len(w.n)
-        adr.adr_timing_enable(steps * (2 * d + 4) + 8)
-        solver.solve(Ud, Vd, steps)
-        torch.cuda.synchronize()
-        n_mode, ms_mode = adr.adr_timing_read(0)
-        n_fused, ms_fused = adr.adr_timing_read(3)
-        adr.adr_timing_enable(0)
-        avg = ms_mode / max(n_mode, 1)
-        flops = 2 * 2.0 * (sum(w.n) / d) * w.N
-        nbytes = 2 * 2 * 4 * w.N
-        tf = flops / (avg * 1e-3) / 1e12
-        gbs = nbytes / (avg * 1e-3) / 1e9
-        if prec == "f32":
-            roof = {"bound": "mfma", "achieved": tf, "peak": PEAKS["f32_mfma_tflops"], "unit": "TFLOP/s",
-                    "frac": tf / PEAKS["f32_mfma_tflops"]}
-        else:
-            roof = {"bound": "hbm", "achieved": gbs, "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
-                    "frac": gbs / PEAKS["hbm_gbs"], "tflops_fp32_equivalent": tf}
-        roof.update({"kernel": f"mode_product_{prec}", "avg_launch_ms": avg, "launches": n_mode,
-                     "flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
-                     "fused_launch_avg_ms": (ms_fused / n_fused) if n_fused else None})
-        out[prec] = {"value": w.N * steps / dt, "ms_per_step": 1e3 * dt / steps, "steps": steps,
-                     "rel_inf_err_vs_f64_gpu": err, "roofline": roof}
+            Ue, Ve = solver.upload(U0, V0)
+            solver.solve(Ue, Ve, ref_steps)
+            torch.cuda.synchronize()
+            err = _rel_err(Ue, Ve, ref_state)
+            del Ue, Ve
+        leg = {"value": w.N * steps / dt, "ms_per_step": 1e3 * dt / steps, "steps": steps,
+               "rel_inf_err_vs_oracle": err, "oracle_steps": ref_steps}
+        if prec != "f64":
+            # a separate pass with HIP events around each launch: the products' roofline
+            d = len(w.n)
+            adr.adr_timing_enable(steps * (2 * d + 4) + 8)
+            solver.solve(Ud, Vd, steps)
+            torch.cuda.synchronize()
+            n_mode, ms_mode = adr.adr_timing_read(0)
+            n_fused, ms_fused = adr.adr_timing_read(3)
+            adr.adr_timing_enable(0)
+            avg = ms_mode / max(n_mode, 1)
+            leg["roofline"] = _lowp_roofline(prec, w, avg, n_mode,
+                                             (ms_fused / n_fused) if n_fused else None)
+        out[prec] = leg
         del solver, Ud, Vd, Ud2, Vd2
     return out
 
 
-def _workload_legs(adr, S, torch, seed):
+def _lowp_roofline(prec, w, avg_ms, launches, fused_avg_ms):
+    """Roofline of one reduced-precision product launch (both components).
+    Algorithmic work: 2 n_mu N flops per component, FP32 operands in and out
+    (8 bytes per point per component).  FP32 is bound by the FP32 matrix rate.
+    A split-BF16 product runs its flops as `parts` BF16 MFMA products, so its
+    matrix-core bound is the BF16 rate divided by that count (in flops of the
+    FP32-equivalent work); against the HBM time of its operands it is the
+    slower of the two that bounds it."""
+    d = len(w.n)
+    flops = 2 * 2.0 * (sum(w.n) / d) * w.N
+    nbytes = 2 * 2 * 4 * w.N
+    tf = flops / (avg_ms * 1e-3) / 1e12
+    gbs = nbytes / (avg_ms * 1e-3) / 1e9
+    rec = {"kernel": f"mode_product_{prec}", "avg_launch_ms": avg_ms, "launches": launches,
+           "flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
+           "hbm_gbs": gbs, "fused_launch_avg_ms": fused_avg_ms}
+    if prec == "f32":
+        rec.update({"bound": "mfma", "achieved": tf, "peak": PEAKS["f32_mfma_tflops"],
+                    "unit": "TFLOP/s", "frac": tf / PEAKS["f32_mfma_tflops"]})
+        return rec
+    parts = SPLIT_PRODUCTS[prec]
+    mfma_peak = PEAKS["bf16_mfma_tflops"] / parts          # FP32-equivalent TFLOP/s
+    t_mfma = flops / (mfma_peak * 1e12)
+    t_hbm = nbytes / (PEAKS["hbm_gbs"] * 1e9)
+    if t_mfma >= t_hbm:
+        rec.update({"bound": "mfma", "achieved": tf, "peak": mfma_peak, "unit": "TFLOP/s",
+                    "frac": tf / mfma_peak,
+                    "peak_derivation": f"{PEAKS['bf16_mfma_tflops']} TFLOP/s BF16 / {parts} products"})
+    else:
+        rec.update({"bound": "hbm", "achieved": gbs, "peak": PEAKS["hbm_gbs"], "unit": "GB/s",
+                    "frac": gbs / PEAKS["hbm_gbs"], "tflops_fp32_equivalent": tf})
+    return rec
+
+
+def _workload_legs(adr, S, torch, seed, with_oracle=True):
     """The other two model workloads at one GPU, FP64: the 2D Schnakenberg 64^2
     (launch-bound at 4096 points) and the 3D FitzHugh-Nagumo 128^3, with the mode
     products' position against the FP64 matrix peak.  The 64^2 problem is also
     stepped as a one-problem grouped plan replayed from a HIP graph."""
     out = {}
-    for name, w, steps in (("schnakenberg2d_64", S.schnakenberg_2d(64, 400), 400),
-                           ("fhn3d_128", S.fhn_3d(128, 200), 200)):
+    # (leg, workload, timed steps, oracle steps: the full configured run of 64^2, a
+    # bounded sample of 128^3)
+    for name, w, steps, osteps in (("schnakenberg2d_64", S.schnakenberg_2d(64, 400), 400, 100),
+                                   ("fhn3d_128", S.fhn_3d(128, 200), 200, 5)):
         solver = adr.Solver(w)
         U0, V0 = S.initial_state(w, seed)
+        err = None
+        if with_oracle:
+            ref, _, _ = oracle_sample(w, seed, osteps)
+            Ue, Ve = solver.upload(U0, V0)
+            solver.solve(Ue, Ve, osteps)
+            torch.cuda.synchronize()
+            err = _rel_err(Ue, Ve, ref)
+            del Ue, Ve
         Ud, Vd = solver.upload(U0, V0)
         solver.solve(Ud, Vd, 3)
         torch.cuda.synchronize()
@@ -217,6 +308,7 @@ def _workload_legs(adr, S, torch, seed):
         tf = flops_step * steps / (ms_products * 1e-3) / 1e12 if ms_products > 0 else None
         leg = {"grid": list(w.n), "steps": steps, "value": w.N * steps / dt,
                "ms_per_step": 1e3 * dt / steps,
+               "rel_inf_err_vs_oracle": err, "oracle_steps": osteps if with_oracle else None,
                "mode_products": {"launches_per_step": (n_mode + n_fused) / steps,
                                  "ms_per_step": ms_products / steps,
                                  "tflops": tf, "peak": PEAKS["f64_mfma_tflops"],
@@ -273,7 +365,7 @@ def _batched_leg(adr, S, torch, steps, seed):
     return out
 
 
-def _serving_leg(S, count, rate, budget_gib, seed):
+def _serving_leg(S, count, rate, budget_gib, seed, low_rate=None):
     """The serving stream: Poisson arrivals of mixed 2D/3D requests, served by the
     continuous-batching engine (second of two passes over the stream) and, for
     comparison, one at a time by the plain FP64 path, on the same arrival
@@ -293,6 +385,21 @@ def _serving_leg(S, count, rate, budget_gib, seed):
     _, seq = serving.run_sequential(be, jobs, keep_results=True)
     keys = ("p50_latency_s", "p99_latency_s", "throughput", "makespan_s", "mean_wait_s",
             "peak_active", "peak_bytes", "rounds", "plans_built", "lanes")
+    low = None
+    if low_rate:
+        # the same requests arriving at a rate both paths keep up with: latency
+        # without queueing (one pass each; the passes above warmed the allocations)
+        lreqs = S.serving_stream(count, low_rate, seed)
+        ljobs = [serving.Job(r.rid, r.arrival, r.workload, r.workload.steps,
+                             lambda k=r.rid: payload[k]) for r in lreqs]
+        eng_low = serving.Engine(be, budget_bytes=budget_gib << 30, max_active=64, max_chunk=16,
+                                 lane_bounds=(4e9,), keep_results=False)
+        eng_low.run(ljobs)
+        _, lseq = serving.run_sequential(be, ljobs, keep_results=False)
+        low = {"rate_per_s": low_rate,
+               "continuous_batching_f64": {k: eng_low.stats[k] for k in keys},
+               "sequential_plain_f64": {k: lseq[k] for k in ("p50_latency_s", "p99_latency_s",
+                                                             "throughput", "makespan_s")}}
     return {
         "workload": f"{count} requests, Poisson rate {rate}/s: 50% 2D Schnakenberg 128^2-1024^2, "
                     "25% 3D FHN, 25% 3D advective Brusselator 32^3-192^3, 50-500 steps, "
@@ -303,6 +410,7 @@ def _serving_leg(S, count, rate, budget_gib, seed):
         "sequential_plain_f64": {k: seq[k] for k in ("p50_latency_s", "p99_latency_s",
                                                      "throughput", "makespan_s")},
         "throughput_unit": "grid-point-steps/s",
+        "below_saturation": low,
     }
 
 
@@ -318,7 +426,11 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=None,
                     help="grid side of the main workload (default 256 / 128 / 64 for "
                          "brusselator3d / fhn3d / schnakenberg2d)")
-    ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--cpu-steps", type=int, default=5,
+                    help="oracle sample: steps from the initial state (the first is untimed); "
+                         "its final state is the reference of every GPU result")
+    ap.add_argument("--cpu-single-steps", type=int, default=1,
+                    help="further oracle steps timed with BLAS on one thread")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true",
@@ -327,6 +439,8 @@ def main(argv=None):
     ap.add_argument("--batch-steps", type=int, default=200)
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-low-rate", type=float, default=5.0,
+                    help="second arrival rate, below saturation (0: skip)")
     ap.add_argument("--serve-budget-gib", type=int, default=16)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of this many MiB three times "
@@ -391,26 +505,37 @@ def main(argv=None):
     n_fused, ms_fused = adr.adr_timing_read(3)
     adr.adr_timing_enable(0)
 
-    if not args.no_extras:
-        # FP64 state after `lowp_steps` steps, the reference of the reduced precisions
-        ref = None
-        if args.precision == "f64" and args.scheme == "etd2rkds":
+    # ---- the oracle on the host's cores: a bounded, timed sample of the same
+    # workload, whose state after `cpu_steps` steps is the reference of every GPU
+    # result below (the main path's and each precision's)
+    cpu_rec, oracle_ref, parity = None, None, None
+    if not args.no_cpu:
+        cpu_rec, ref_state = cpu_baseline(w, args.seed, args.cpu_steps, args.cpu_single_steps)
+        oracle_ref = (args.cpu_steps, ref_state)
+        if args.scheme == "etd2rkds":
             Ud.copy_(U_init)
             Vd.copy_(V_init)
-            solver.solve(Ud, Vd, args.lowp_steps)
+            solver.solve(Ud, Vd, args.cpu_steps)
             torch.cuda.synchronize()
-            ref = (Ud.clone(), Vd.clone())
+            parity = {"rel_inf_err_vs_oracle": _rel_err(Ud, Vd, ref_state),
+                      "steps": args.cpu_steps, "precision": args.precision}
+        else:
+            oracle_ref = None
+
+    if not args.no_extras:
         del U_init, V_init, Ud, Vd, solver
         torch.cuda.empty_cache()
-        extras = {"precisions": _lowp_legs(adr, S, torch, w, args.lowp_steps, args.seed, ref)}
-        del ref
+        others = tuple(p for p in ("f32", "bf16x3") if p != args.precision)
+        extras = {"precisions": _precision_legs(adr, S, torch, w, args.lowp_steps, args.seed,
+                                                oracle_ref, others)}
         torch.cuda.empty_cache()
-        extras["workloads"] = _workload_legs(adr, S, torch, args.seed)
+        extras["workloads"] = _workload_legs(adr, S, torch, args.seed, not args.no_cpu)
         torch.cuda.empty_cache()
         extras["batched"] = _batched_leg(adr, S, torch, args.batch_steps, args.seed)
         torch.cuda.empty_cache()
         extras["serving"] = _serving_leg(S, args.serve_requests, args.serve_rate,
-                                         args.serve_budget_gib, args.seed)
+                                         args.serve_budget_gib, args.seed,
+                                         args.serve_low_rate or None)
     else:
         extras = {}
 
@@ -419,21 +544,36 @@ def main(argv=None):
     mode_avg_ms = ms_mode / max(n_mode, 1)
     # algorithmic work of one mode-product launch: both components, 2*n_mu*N flops each
     flops_per_launch = 2 * 2.0 * (sum(w.n) / d) * N
-    elem = {"f64": 8, "f32": 4, "bf16x3": 4}[args.precision]
-    peak = {"f64": PEAKS["f64_mfma_tflops"], "f32": PEAKS["f32_mfma_tflops"],
-            "bf16x3": PEAKS["bf16_mfma_tflops"]}[args.precision]
-    achieved = flops_per_launch / (mode_avg_ms * 1e-3) / 1e12
-    bytes_per_launch = 2 * 2 * elem * N  # read + write one tensor per component
     # the product launch of a step whose epilogue also computes a stage (timed apart),
     # 32 B/point more than a plain launch in both cases: FP64 reads the states C_n
     # (16 B) and writes R2 (16 B); reduced precision reads C_n (16 B) and D1 (8 B) and
     # writes FP64 instead of FP32 (8 B)
     fused_avg_ms = ms_fused / n_fused if n_fused else None
+    if args.precision == "f64":
+        achieved = flops_per_launch / (mode_avg_ms * 1e-3) / 1e12
+        bytes_per_launch = 2 * 2 * 8 * N  # read + write one tensor per component
+        roof = {"kernel": "mode_product_f64", "bound": "mfma", "achieved": achieved,
+                "peak": PEAKS["f64_mfma_tflops"], "unit": "TFLOP/s",
+                "frac": achieved / PEAKS["f64_mfma_tflops"],
+                "avg_launch_ms": mode_avg_ms, "launches": n_mode,
+                "flops_per_launch": flops_per_launch,
+                "algorithmic_bytes_per_launch": bytes_per_launch}
+    else:
+        roof = _lowp_roofline(args.precision, w, mode_avg_ms, n_mode, fused_avg_ms)
+        bytes_per_launch = roof["algorithmic_bytes_per_launch"]
+    roof["tflops"] = flops_per_launch / (mode_avg_ms * 1e-3) / 1e12
+    roof["traffic"] = _traffic_from_profiles(args.precision, w.name)
     fused_bytes = bytes_per_launch + 32 * N
-    # split BF16: three products' MFMA time (3 x flops at 2.5 PFLOP/s) is below the
-    # time to move its FP32 operands, so its roofline is HBM
-    hbm_bound = args.precision == "bf16x3"
-    traffic = _traffic_from_profiles(args.precision, w.name)
+    roof["fused_launch"] = None if fused_avg_ms is None else {
+        "what": ("last product of the phi_1 operator, stage 2 in its epilogue"
+                 if args.precision == "f64" else
+                 "last product of the phi_2 operator, writes C_n + D1 + D2 in FP64"),
+        "launches": n_fused,
+        "avg_launch_ms": fused_avg_ms,
+        "tflops": flops_per_launch / (fused_avg_ms * 1e-3) / 1e12,
+        "algorithmic_bytes_per_launch": fused_bytes,
+        "hbm_gbs": fused_bytes / (fused_avg_ms * 1e-3) / 1e9,
+    }
     stage_avg_ms = ms_stage / max(n_stage, 1)
     # algorithmic bytes per point of the stage kernels, averaged over the launches of a step:
     # FP64: stage 1 (read U,V; write R1u,R1v) 32 B, and stage 2 (read U,V,U2,V2; write R2)
@@ -462,31 +602,7 @@ def main(argv=None):
         "config": {"workload": w.name, "grid": list(w.n), "scheme": args.scheme,
                    "precision": args.precision, "tau": w.tau, "seed": args.seed,
                    "model": model_text},
-        "roofline": {
-            "kernel": f"mode_product_{args.precision}",
-            "bound": "hbm" if hbm_bound else "mfma",
-            "achieved": (bytes_per_launch / (mode_avg_ms * 1e-3) / 1e9) if hbm_bound else achieved,
-            "peak": PEAKS["hbm_gbs"] if hbm_bound else peak,
-            "unit": "GB/s" if hbm_bound else "TFLOP/s",
-            "frac": ((bytes_per_launch / (mode_avg_ms * 1e-3) / 1e9) / PEAKS["hbm_gbs"]) if hbm_bound
-                    else achieved / peak,
-            "tflops": achieved,
-            "traffic": traffic,
-            "avg_launch_ms": mode_avg_ms,
-            "launches": n_mode,
-            "flops_per_launch": flops_per_launch,
-            "algorithmic_bytes_per_launch": bytes_per_launch,
-            "fused_launch": None if fused_avg_ms is None else {
-                "what": ("last product of the phi_1 operator, stage 2 in its epilogue"
-                         if args.precision == "f64" else
-                         "last product of the phi_2 operator, writes C_n + D1 + D2 in FP64"),
-                "launches": n_fused,
-                "avg_launch_ms": fused_avg_ms,
-                "tflops": flops_per_launch / (fused_avg_ms * 1e-3) / 1e12,
-                "algorithmic_bytes_per_launch": fused_bytes,
-                "hbm_gbs": fused_bytes / (fused_avg_ms * 1e-3) / 1e9,
-            },
-        },
+        "roofline": roof,
         "stage_kernels": {
             "bound": "hbm",
             "avg_launch_ms": stage_avg_ms,
@@ -504,13 +620,16 @@ def main(argv=None):
         "paper_context": "paper (MATLAB, i7-10750H 6 cores): 64^3 Brusselator ETD2RKds 9.1e-3 s/step "
                          "= 2.9e7 grid-point-steps/s",
     }
+    if parity is not None:
+        line["parity"] = parity
     if extras:
-        if args.precision == "f64":
-            extras["precisions"]["f64"] = {"value": value, "ms_per_step": ms_per_step,
-                                           "steps": args.steps}
+        extras["precisions"][args.precision] = {
+            "value": value, "ms_per_step": ms_per_step, "steps": args.steps,
+            "rel_inf_err_vs_oracle": parity["rel_inf_err_vs_oracle"] if parity else None,
+            "oracle_steps": args.cpu_steps if parity else None}
         line.update(extras)
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    if cpu_rec is not None:
+        line["cpu_baseline"] = cpu_rec
     print(json.dumps(line), flush=True)
     return 0
 

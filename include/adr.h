@@ -258,8 +258,7 @@ int adr_solve_monitored(const adr_problem* p, double* U, double* V, int nsteps, 
  *               built on a side stream while other plans run elsewhere
  *   plan        receives the plan
  * The plan's device tables come from a pool that destroyed plans return to
- * (no device-wide synchronisation on destroy).  A plan may be destroyed once
- * no run of it is pending on any stream.
+ * (no device-wide synchronisation on destroy; see adr_batch_destroy).
  * Errors: ADR_EINVAL, ADR_ENOMEM (a workspace too small, or no device memory
  * for the tables), ADR_ENOTSUP (scheme, precision or a missing band),
  * ADR_EDEVICE.
@@ -283,7 +282,11 @@ int adr_batch_run(adr_batch* plan, int nsteps, void* stream);
  * max_phases == 0).
  */
 int adr_batch_info(const adr_batch* plan, int* tile_cfg, int max_phases, int* graph_captured);
-/* adr_batch_destroy -- release the plan (the caller's buffers are untouched). */
+/* adr_batch_destroy -- release the plan (the caller's buffers are untouched).
+ * First waits, on the host, for the steps that adr_batch_run enqueued for
+ * this plan on any stream (only this plan's work, no device-wide wait), so a
+ * plan may be destroyed right after an asynchronous run: its job tables are
+ * handed to the next plan only once no queued kernel can read them. */
 int adr_batch_destroy(adr_batch* plan);
 
 /*

@@ -80,18 +80,19 @@ def precompute(p: Problem):
     return mats
 
 
-def etd2rkds_step(U, V, p: Problem, mats):
-    """One step of eq. (11)."""
+def etd2rkds_step(U, V, p: Problem, mats, order=None):
+    """One step of eq. (11).  ``order``: direction order of the Tucker operators
+    (default mu = 1..d; see ``tucker``)."""
     tau, d = p.tau, p.d
     Gu, Gv = reaction(p.model, p.params, U, V)
     Ru = kron_sum_action(U, p.A[0]) + Gu
     Rv = kron_sum_action(V, p.A[1]) + Gv
-    U2 = U + tau * tucker(Ru, mats[0][1])
-    V2 = V + tau * tucker(Rv, mats[1][1])
+    U2 = U + tau * tucker(Ru, mats[0][1], order)
+    V2 = V + tau * tucker(Rv, mats[1][1], order)
     Gu2, Gv2 = reaction(p.model, p.params, U2, V2)
     c2 = 2.0 ** (d - 1)
-    U1 = U2 + c2 * tau * tucker(Gu2 - Gu, mats[0][2])
-    V1 = V2 + c2 * tau * tucker(Gv2 - Gv, mats[1][2])
+    U1 = U2 + c2 * tau * tucker(Gu2 - Gu, mats[0][2], order)
+    V1 = V2 + c2 * tau * tucker(Gv2 - Gv, mats[1][2], order)
     return np.asfortranarray(U1), np.asfortranarray(V1)
 
 
@@ -144,12 +145,17 @@ def split_phi_dense(As, tau: float, ell: int) -> np.ndarray:
     return (math.factorial(ell) ** (d - 1)) * M
 
 
-def solve(U0, V0, p: Problem, steps: int, scheme: str = "etd2rkds", mats=None):
-    """Advance (U0, V0) by ``steps`` constant steps of the chosen scheme."""
+def solve(U0, V0, p: Problem, steps: int, scheme: str = "etd2rkds", mats=None, order=None):
+    """Advance (U0, V0) by ``steps`` constant steps of the chosen scheme
+    (``order``: Tucker direction order of ETD2RKds, default mu = 1..d)."""
     if mats is None:
         mats = precompute(p)
-    step = {"etd2rkds": etd2rkds_step, "lawson2b": lawson2b_step}[scheme]
     U, V = np.asfortranarray(U0, dtype=np.float64), np.asfortranarray(V0, dtype=np.float64)
     for _ in range(steps):
-        U, V = step(U, V, p, mats)
+        if scheme == "etd2rkds":
+            U, V = etd2rkds_step(U, V, p, mats, order)
+        elif scheme == "lawson2b":
+            U, V = lawson2b_step(U, V, p, mats)
+        else:
+            raise KeyError(scheme)
     return U, V

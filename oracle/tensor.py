@@ -38,11 +38,17 @@ def mode_product(W: np.ndarray, M: np.ndarray, mu: int) -> np.ndarray:
     return np.moveaxis(out, 0, mu)
 
 
-def tucker(W: np.ndarray, Ms) -> np.ndarray:
-    """W x_1 M_1 x_2 M_2 ... x_d M_d  (eq. (5)), applied in the order mu = 1..d."""
+def tucker(W: np.ndarray, Ms, order=None) -> np.ndarray:
+    """W x_1 M_1 x_2 M_2 ... x_d M_d  (eq. (5)), applied in the order mu = 1..d.
+
+    ``order`` (a permutation of the 0-based directions) applies the same
+    products in another order.  Mode products along different directions
+    commute (each acts on its own index), so every order gives the same
+    operator; only the rounding differs.  Used to measure how far rounding
+    alone moves a long run."""
     out = W
-    for mu, M in enumerate(Ms):
-        out = mode_product(out, M, mu)
+    for mu in (range(len(Ms)) if order is None else order):
+        out = mode_product(out, Ms[mu], mu)
     return np.asfortranarray(out)
 
 

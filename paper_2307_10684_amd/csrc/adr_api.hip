@@ -453,6 +453,93 @@ hipError_t gemm(int n, const double* A, const double* B, double* C, double alpha
 
 }  // namespace
 
+namespace adr {
+namespace host {
+
+// The body of adr_precompute_phi on a caller-chosen scratch: degree-18 Taylor
+// polynomials of the scaled matrix, then the modified squarings.
+int precompute_phi_in(int n, const double* A_dev, double tau, double* const outs[3],
+                      double* base, hipStream_t s) {
+  const size_t nn = (size_t)n * n;
+  // buffers: Y^1..Y^6, block B, Horner H, current E/P1/P2, next E/P1/P2, norm
+  constexpr int kBuf = 14;
+  double* Yp[7];
+  for (int j = 1; j <= 6; ++j) Yp[j] = base + nn * (j - 1);
+  double* Bb = base + nn * 6;
+  double* H = base + nn * 7;
+  double* cur[3] = {base + nn * 8, base + nn * 9, base + nn * 10};
+  double* nxt[3] = {base + nn * 11, base + nn * 12, base + nn * 13};
+  double* dnorm = base + nn * kBuf;
+  int status = ADR_OK;
+  auto fail = [&](int st) {
+    (void)hipStreamSynchronize(s);
+    return st;
+  };
+  // ||tau A||_1 sets the scaling power s with ||tau A / 2^s||_1 <= 1
+  if (launch_norm1(n, A_dev, tau, dnorm, s) != hipSuccess) return fail(ADR_EDEVICE);
+  double norm = 0.0;
+  if (hipMemcpyAsync(&norm, dnorm, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return fail(ADR_EDEVICE);
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(ADR_EDEVICE);
+  if (!std::isfinite(norm)) return fail(ADR_ENONFINITE);
+  int sq = 0;
+  if (norm > 1.0) sq = (int)std::ceil(std::log2(norm));
+  const double scale = std::ldexp(tau, -sq);
+  hipError_t e = launch_scale_copy((long long)nn, A_dev, scale, Yp[1], s);
+  for (int j = 2; j <= 6 && e == hipSuccess; ++j)
+    e = gemm(n, Yp[j - 1], Yp[1], Yp[j], 1.0, 0.0, nullptr, 0.0, nullptr, s);
+  if (e != hipSuccess) return fail(ADR_EDEVICE);
+  // Taylor polynomials of degree 18 of exp, phi_1, phi_2 (coefficients 1/(k+l)!) in
+  // Paterson-Stockmeyer form: p = B0 + (B1 + (B2 + c18 Y^6) Y^6) Y^6, Bj = sum_i c_{6j+i} Y^i
+  for (int l = 0; l < 3 && e == hipSuccess; ++l) {
+    double coef[19];
+    double f = 1.0;
+    for (int j = 1; j <= l; ++j) f *= j;  // l!
+    for (int k = 0; k <= 18; ++k) {
+      coef[k] = 1.0 / f;                  // 1/(k+l)!
+      f *= (double)(k + l + 1);
+    }
+    auto block = [&](int j, double* out, bool add_top) {
+      const double* P[8];
+      double c[8];
+      int cnt = 0;
+      for (int i = 1; i <= 5; ++i) {
+        P[cnt] = Yp[i];
+        c[cnt] = coef[6 * j + i];
+        ++cnt;
+      }
+      if (add_top) {
+        P[cnt] = Yp[6];
+        c[cnt] = coef[18];
+        ++cnt;
+      }
+      return launch_lincomb(n, cnt, P, c, coef[6 * j], out, s);
+    };
+    e = block(2, H, true);                                                           // H = B2 + c18 Y^6
+    if (e == hipSuccess) e = block(1, Bb, false);                                    // B1
+    if (e == hipSuccess) e = gemm(n, H, Yp[6], nxt[l], 1.0, 1.0, Bb, 0.0, nullptr, s);  // H Y^6 + B1
+    if (e == hipSuccess) e = block(0, Bb, false);                                    // B0
+    if (e == hipSuccess) e = gemm(n, nxt[l], Yp[6], cur[l], 1.0, 1.0, Bb, 0.0, nullptr, s);
+  }
+  if (e != hipSuccess) return fail(ADR_EDEVICE);
+  // modified squaring: e^{2X} = (e^X)^2, phi_1(2X) = (e^X phi_1 + phi_1)/2,
+  // phi_2(2X) = (e^X phi_2 + phi_1 + phi_2)/4
+  for (int it = 0; it < sq && e == hipSuccess; ++it) {
+    e = gemm(n, cur[0], cur[2], nxt[2], 0.25, 0.25, cur[1], 0.25, cur[2], s);
+    if (e == hipSuccess) e = gemm(n, cur[0], cur[1], nxt[1], 0.5, 0.5, cur[1], 0.0, nullptr, s);
+    if (e == hipSuccess) e = gemm(n, cur[0], cur[0], nxt[0], 1.0, 0.0, nullptr, 0.0, nullptr, s);
+    for (int j = 0; j < 3; ++j) std::swap(cur[j], nxt[j]);
+  }
+  for (int j = 0; j < 3 && e == hipSuccess; ++j)
+    if (outs[j]) e = launch_copy_f64(cur[j], outs[j], nn, s);
+  if (e != hipSuccess) return fail(ADR_EDEVICE);
+  if (hipStreamSynchronize(s) != hipSuccess) status = ADR_EDEVICE;
+  return status;
+}
+
+}  // namespace host
+}  // namespace adr
+
 // ====================================================================== ABI
 
 // scratch of adr_precompute_phi, per device
@@ -524,9 +611,6 @@ int adr_precompute_phi(int n, const double* A_dev, double tau, double* E_dev, do
   if (n < 1 || n > 4096 || !A_dev || !std::isfinite(tau) || tau == 0.0) return ADR_EINVAL;
   if (!E_dev && !P1_dev && !P2_dev) return ADR_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t nn = (size_t)n * n;
-  // buffers: Y^1..Y^6, block B, Horner H, current E/P1/P2, next E/P1/P2, norm
-  constexpr int kBuf = 14;
   // The scratch is a per-device block that grows and is kept (the call ends
   // with a synchronisation of `s`, so the next call can reuse it).  Freeing
   // it would wait for the whole device, stalling unrelated streams.
@@ -534,7 +618,7 @@ int adr_precompute_phi(int n, const double* A_dev, double tau, double* E_dev, do
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return ADR_EDEVICE;
   PhiScratch& sc = g_phi_scratch[dev];
-  const size_t need = sizeof(double) * (nn * kBuf + 1);
+  const size_t need = sizeof(double) * phi_scratch_doubles(n);
   if (sc.cap < need) {
     if (sc.ptr) {
       (void)hipStreamSynchronize(s);
@@ -545,80 +629,8 @@ int adr_precompute_phi(int n, const double* A_dev, double tau, double* E_dev, do
     if (hipMalloc(&sc.ptr, need) != hipSuccess) return ADR_ENOMEM;
     sc.cap = need;
   }
-  double* base = static_cast<double*>(sc.ptr);
-  double* Yp[7];
-  for (int j = 1; j <= 6; ++j) Yp[j] = base + nn * (j - 1);
-  double* Bb = base + nn * 6;
-  double* H = base + nn * 7;
-  double* cur[3] = {base + nn * 8, base + nn * 9, base + nn * 10};
-  double* nxt[3] = {base + nn * 11, base + nn * 12, base + nn * 13};
-  double* dnorm = base + nn * kBuf;
-  int status = ADR_OK;
-  auto fail = [&](int st) {
-    (void)hipStreamSynchronize(s);
-    return st;
-  };
-  // ||tau A||_1 sets the scaling power s with ||tau A / 2^s||_1 <= 1
-  if (launch_norm1(n, A_dev, tau, dnorm, s) != hipSuccess) return fail(ADR_EDEVICE);
-  double norm = 0.0;
-  if (hipMemcpyAsync(&norm, dnorm, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
-    return fail(ADR_EDEVICE);
-  if (hipStreamSynchronize(s) != hipSuccess) return fail(ADR_EDEVICE);
-  if (!std::isfinite(norm)) return fail(ADR_ENONFINITE);
-  int sq = 0;
-  if (norm > 1.0) sq = (int)std::ceil(std::log2(norm));
-  const double scale = std::ldexp(tau, -sq);
-  hipError_t e = launch_scale_copy((long long)nn, A_dev, scale, Yp[1], s);
-  for (int j = 2; j <= 6 && e == hipSuccess; ++j)
-    e = gemm(n, Yp[j - 1], Yp[1], Yp[j], 1.0, 0.0, nullptr, 0.0, nullptr, s);
-  if (e != hipSuccess) return fail(ADR_EDEVICE);
-  // Taylor polynomials of degree 18 of exp, phi_1, phi_2 (coefficients 1/(k+l)!) in
-  // Paterson-Stockmeyer form: p = B0 + (B1 + (B2 + c18 Y^6) Y^6) Y^6, Bj = sum_i c_{6j+i} Y^i
-  for (int l = 0; l < 3 && e == hipSuccess; ++l) {
-    double coef[19];
-    double f = 1.0;
-    for (int j = 1; j <= l; ++j) f *= j;  // l!
-    for (int k = 0; k <= 18; ++k) {
-      coef[k] = 1.0 / f;                  // 1/(k+l)!
-      f *= (double)(k + l + 1);
-    }
-    auto block = [&](int j, double* out, bool add_top) {
-      const double* P[8];
-      double c[8];
-      int cnt = 0;
-      for (int i = 1; i <= 5; ++i) {
-        P[cnt] = Yp[i];
-        c[cnt] = coef[6 * j + i];
-        ++cnt;
-      }
-      if (add_top) {
-        P[cnt] = Yp[6];
-        c[cnt] = coef[18];
-        ++cnt;
-      }
-      return launch_lincomb(n, cnt, P, c, coef[6 * j], out, s);
-    };
-    e = block(2, H, true);                                                           // H = B2 + c18 Y^6
-    if (e == hipSuccess) e = block(1, Bb, false);                                    // B1
-    if (e == hipSuccess) e = gemm(n, H, Yp[6], nxt[l], 1.0, 1.0, Bb, 0.0, nullptr, s);  // H Y^6 + B1
-    if (e == hipSuccess) e = block(0, Bb, false);                                    // B0
-    if (e == hipSuccess) e = gemm(n, nxt[l], Yp[6], cur[l], 1.0, 1.0, Bb, 0.0, nullptr, s);
-  }
-  if (e != hipSuccess) return fail(ADR_EDEVICE);
-  // modified squaring: e^{2X} = (e^X)^2, phi_1(2X) = (e^X phi_1 + phi_1)/2,
-  // phi_2(2X) = (e^X phi_2 + phi_1 + phi_2)/4
-  for (int it = 0; it < sq && e == hipSuccess; ++it) {
-    e = gemm(n, cur[0], cur[2], nxt[2], 0.25, 0.25, cur[1], 0.25, cur[2], s);
-    if (e == hipSuccess) e = gemm(n, cur[0], cur[1], nxt[1], 0.5, 0.5, cur[1], 0.0, nullptr, s);
-    if (e == hipSuccess) e = gemm(n, cur[0], cur[0], nxt[0], 1.0, 0.0, nullptr, 0.0, nullptr, s);
-    for (int j = 0; j < 3; ++j) std::swap(cur[j], nxt[j]);
-  }
   double* outs[3] = {E_dev, P1_dev, P2_dev};
-  for (int j = 0; j < 3 && e == hipSuccess; ++j)
-    if (outs[j]) e = launch_copy_f64(cur[j], outs[j], nn, s);
-  if (e != hipSuccess) return fail(ADR_EDEVICE);
-  if (hipStreamSynchronize(s) != hipSuccess) status = ADR_EDEVICE;
-  return status;
+  return precompute_phi_in(n, A_dev, tau, outs, static_cast<double*>(sc.ptr), s);
 }
 
 size_t adr_workspace_bytes(const adr_problem* p) {

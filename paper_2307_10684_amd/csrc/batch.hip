@@ -126,6 +126,9 @@ struct adr_batch {
   hipGraphExec_t exec = nullptr;
   hipStream_t cap = nullptr;
   bool autotuned = false;
+  // one event per stream that adr_batch_run used, recorded after its last
+  // enqueued step: destroy waits for them before the tables go back to the pool
+  std::vector<std::pair<hipStream_t, hipEvent_t>> runs;
 };
 
 namespace {
@@ -271,6 +274,13 @@ TileCfg default_cfg(const adr_batch& b, int mu) {
 
 void destroy(adr_batch* b) {
   if (!b) return;
+  // kernels of runs still queued read the job tables and may replay the graph:
+  // wait for them (a host wait on this plan's work only) before releasing either
+  for (auto& r : b->runs) {
+    (void)hipEventSynchronize(r.second);
+    (void)hipEventDestroy(r.second);
+  }
+  b->runs.clear();
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);
@@ -578,12 +588,25 @@ int adr_batch_create(int count, const adr_problem* problems, double* const* U, d
 
 int adr_batch_run(adr_batch* plan, int nsteps, void* stream) {
   if (!plan || nsteps < 0) return ADR_EINVAL;
+  if (nsteps == 0) return ADR_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t* done = nullptr;
+  for (auto& r : plan->runs)
+    if (r.first == s) done = &r.second;
+  if (!done) {
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return ADR_EDEVICE;
+    plan->runs.emplace_back(s, ev);
+    done = &plan->runs.back().second;
+  }
   for (int it = 0; it < nsteps; ++it) {
     const hipError_t e = plan->exec ? hipGraphLaunch(plan->exec, s) : batch_step(*plan, s, false);
-    if (e != hipSuccess) return ADR_EDEVICE;
+    if (e != hipSuccess) {
+      (void)hipEventRecord(*done, s);
+      return ADR_EDEVICE;
+    }
   }
-  return ADR_OK;
+  return hipEventRecord(*done, s) == hipSuccess ? ADR_OK : ADR_EDEVICE;
 }
 
 int adr_batch_info(const adr_batch* plan, int* tile_cfg, int max_phases, int* graph_captured) {

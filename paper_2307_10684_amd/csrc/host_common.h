@@ -77,6 +77,14 @@ struct Carve {
 };
 
 Carve carve(const adr_problem* p, const Geometry& g, char* base);
+
+// Matrix functions of adr_precompute_phi for one n x n matrix, worked out in
+// `base` (device, phi_scratch_doubles(n) doubles, 256-byte aligned).  outs[j]
+// (E, phi_1, phi_2) may be null.  Synchronises `s` twice (the 1-norm read-back
+// and before returning).  Returns an adr_status.
+constexpr size_t phi_scratch_doubles(int n) { return (size_t)n * n * 14 + 1; }
+int precompute_phi_in(int n, const double* A_dev, double tau, double* const outs[3],
+                      double* base, hipStream_t s);
 int check_problem(const adr_problem* p, Geometry& g);
 Reaction reaction_of(const adr_problem* p);
 hipError_t prepare_lowp(const adr_problem* p, const Geometry& g, const Carve& c, hipStream_t s);

@@ -63,8 +63,31 @@ def test_committed_stage_summary_matches_the_kernel_source():
 
 
 def test_cpu_baseline_record():
-    w = S.schnakenberg_2d(16, 2)
-    rec = bench.cpu_baseline(w, 2)
+    import numpy as np
+    import oracle as O
+    w = S.schnakenberg_2d(16, 3)
+    rec, ref = bench.cpu_baseline(w, 0, steps=3, single_steps=1)
     assert rec["kind"] == "oracle" and rec["unit"] == "grid-point-steps/s"
     assert rec["value"] > 0 and rec["cores"] >= 1
-    assert "schnakenberg2d_16" in rec["sample"]
+    assert "schnakenberg2d_16" in rec["sample"] and rec["cpu_model"]
+    assert rec["single_thread"]["cores"] == 1 and rec["single_thread"]["value"] > 0
+    # the reference state is the oracle's after exactly `steps` steps
+    U0, V0 = S.initial_state(w, 0)
+    U, V = O.solve(U0, V0, O.problem_from_workload(w), 3)
+    assert np.array_equal(ref[0], U) and np.array_equal(ref[1], V)
+
+
+def test_reduced_precision_roofline_bounds():
+    # FP32: the FP32 matrix rate; split BF16 with three products at n = 256: the
+    # matrix cores' time (3 x 2n flops at 2.5 PFLOP/s) is below the time to move
+    # the FP32 operands, so HBM bounds it
+    w = S.brusselator_3d()
+    r32 = bench._lowp_roofline("f32", w, 0.160, 100, None)
+    assert r32["bound"] == "mfma" and r32["peak"] == bench.PEAKS["f32_mfma_tflops"]
+    assert abs(r32["achieved"] - 17.179869184e9 / 0.160e-3 / 1e12) < 1e-9
+    r3 = bench._lowp_roofline("bf16x3", w, 0.085, 100, None)
+    parts = bench.SPLIT_PRODUCTS["bf16x3"]
+    t_mfma = parts * 17.179869184e9 / 2.5e15
+    t_hbm = 4 * 4 * w.N / 8e12
+    assert r3["bound"] == ("mfma" if t_mfma >= t_hbm else "hbm")
+    assert 0 < r3["frac"] < 1

@@ -196,3 +196,24 @@ def test_batched_schnakenberg_64(dev, precision, steps):
         e = _err(got[k], (U, V))
         print(f"instance {k} side {w.n[0]} ({precision}): rel inf err vs oracle {e:.2e}")
         assert e <= TOL[precision]
+
+
+def test_destroy_right_after_async_run(dev, mix_ref):
+    # plan A runs on a side stream and is destroyed at once, without a
+    # synchronisation; plan B, built right after, may take A's pooled job-table
+    # block.  destroy waits for A's queued steps first, so both stay exact.
+    import torch
+    side = torch.cuda.Stream()
+    sa, sta = _setup(dev, MIX[:3] + MIX[6:], mix_ref[:3] + mix_ref[6:])
+    torch.cuda.synchronize()
+    a = dev.Batch(sa, sta, dev.ADR_BATCH_GRAPH, stream=side)
+    a.run(STEPS)
+    a.close()
+    sb, stb = _setup(dev, MIX[3:6], mix_ref[3:6])
+    b = dev.Batch(sb, stb)
+    b.run(STEPS)
+    torch.cuda.synchronize()
+    b.close()
+    for s, st, r in zip(sa + sb, sta + stb, mix_ref[:3] + mix_ref[6:] + mix_ref[3:6]):
+        e = _err(s.download(*st), (r[2], r[3]))
+        assert e <= TOL["f64"], (s.workload.name, e)

@@ -60,6 +60,19 @@ def test_mode_products_commute():
     assert np.allclose(a, b, rtol=1e-14, atol=1e-14)
 
 
+def test_tucker_any_direction_order():
+    # every order of the d products gives (M_d x ... x M_1) vec(W) (numpy.kron form)
+    import itertools
+    rng = np.random.default_rng(3)
+    W = np.asfortranarray(rng.standard_normal((3, 4, 5)))
+    Ms = [rng.standard_normal((n, n)) for n in W.shape]
+    big = np.kron(np.kron(Ms[2], Ms[1]), Ms[0])
+    rhs = big @ W.reshape(-1, order="F")
+    for order in itertools.permutations(range(3)):
+        lhs = O.vec(O.tucker(W, Ms, order))
+        assert np.abs(lhs - rhs).max() <= 1e-13 * np.abs(rhs).max(), order
+
+
 def test_kron_sum_action_matches_dense():
     # K vec(W) = vec(sum_mu W x_mu A_mu), eq. (6); K from the brute-force-pinned kron_sum_dense
     rng = np.random.default_rng(4)
