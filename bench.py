@@ -45,9 +45,10 @@ PEAKS = {  # published MI355X dense peaks
     "hbm_gbs": 8000.0,
 }
 MODE_SRC = {"f64": "mode_product_f64.hip", "f32": "mode_product_lowp.hip",
-            "bf16x3": "mode_product_lowp.hip"}
-# BF16 MFMA products per FP32-equivalent product of a split-BF16 precision
-SPLIT_PRODUCTS = {"bf16x3": 3}
+            "bf16x3": "mode_product_lowp.hip", "bf16x2": "mode_product_lowp.hip"}
+# BF16 MFMA products per FP32-equivalent product of a split-BF16 precision:
+# three parts (hi, mid, lo) take six, two parts (hi, lo) three
+SPLIT_PRODUCTS = {"bf16x3": 6, "bf16x2": 3}
 
 
 def _src_hash(name: str) -> str:
@@ -419,7 +420,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16x3"])
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "bf16x3", "bf16x2"])
     ap.add_argument("--scheme", default="etd2rkds", choices=["etd2rkds", "lawson2b"])
     ap.add_argument("--workload", default="brusselator3d", choices=sorted(WORKLOADS),
                     help="main workload (the default is the benchmark's; the others are for profiling)")
@@ -525,7 +526,7 @@ def main(argv=None):
     if not args.no_extras:
         del U_init, V_init, Ud, Vd, solver
         torch.cuda.empty_cache()
-        others = tuple(p for p in ("f32", "bf16x3") if p != args.precision)
+        others = tuple(p for p in ("f32", "bf16x3", "bf16x2") if p != args.precision)
         extras = {"precisions": _precision_legs(adr, S, torch, w, args.lowp_steps, args.seed,
                                                 oracle_ref, others)}
         torch.cuda.empty_cache()

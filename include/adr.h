@@ -50,9 +50,17 @@ enum adr_status {
 enum adr_bc { ADR_BC_NEUMANN = 0 };                 /* homogeneous Neumann, Sec. 1 */
 enum adr_scheme { ADR_ETD2RKDS = 0,                 /* Sec. 3, eq. (11) */
                   ADR_LAWSON2B = 1 };               /* Sec. 2, eq. (7)  */
+/* Precision of the bulk mode products (the state, the stage combinations and
+ * the small matrix functions stay FP64 in every mode):
+ *   ADR_BF16X3: each FP32 operand split into three bf16 parts hi + mid + lo
+ *     (exact for FP32 values), six bf16 MFMA products (hi hi, hi mid, mid hi,
+ *     hi lo, mid mid, lo hi) accumulated in FP32; close to FP32 accuracy.
+ *   ADR_BF16X2: two parts hi + lo, three products (hi hi, hi lo, lo hi),
+ *     about 2^-16 relative per product: faster, less accurate. */
 enum adr_precision { ADR_F64 = 0,                   /* all arithmetic in FP64 */
                      ADR_F32 = 1,                   /* mode products in FP32 */
-                     ADR_BF16X3 = 2 };              /* mode products in 3-term split BF16 */
+                     ADR_BF16X3 = 2,                /* 3-part split BF16, 6 products */
+                     ADR_BF16X2 = 3 };              /* 2-part split BF16, 3 products */
 /* Reaction models G^u, G^v and the order of adr_problem.params:
  *   ADR_SCHNAKENBERG (gamma, a, b):   gamma(a - u + u^2 v),  gamma(b - u^2 v)    Sec. 4.1 eq. (12)
  *   ADR_FHN          (rho, eps, a1, a0): rho(u - u^3 - v),  rho eps(u - a1 v - a0)  Secs. 4.2-4.3

@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libadr.so")
 ADR_OK, ADR_EINVAL, ADR_ENOMEM, ADR_EDEVICE, ADR_ENOTSUP, ADR_ENONFINITE = 0, -1, -2, -3, -4, -5
 ADR_BC_NEUMANN = 0
 ADR_ETD2RKDS, ADR_LAWSON2B = 0, 1
-ADR_F64, ADR_F32, ADR_BF16X3 = 0, 1, 2
+ADR_F64, ADR_F32, ADR_BF16X3, ADR_BF16X2 = 0, 1, 2, 3
 ADR_SCHNAKENBERG, ADR_FHN, ADR_BRUSSELATOR, ADR_ZERO, ADR_DIB = 0, 1, 2, 3, 4
 ADR_MAX_PARAMS = 12
 ADR_BATCH_AUTOTUNE, ADR_BATCH_GRAPH, ADR_BATCH_PREPARED = 1, 2, 4
@@ -38,7 +38,7 @@ def ADR_BATCH_TILE(cfg: int) -> int:
 MODEL_IDS = {"schnakenberg": ADR_SCHNAKENBERG, "fhn": ADR_FHN,
              "brusselator": ADR_BRUSSELATOR, "zero": ADR_ZERO, "dib": ADR_DIB}
 SCHEME_IDS = {"etd2rkds": ADR_ETD2RKDS, "lawson2b": ADR_LAWSON2B}
-PRECISION_IDS = {"f64": ADR_F64, "f32": ADR_F32, "bf16x3": ADR_BF16X3}
+PRECISION_IDS = {"f64": ADR_F64, "f32": ADR_F32, "bf16x3": ADR_BF16X3, "bf16x2": ADR_BF16X2}
 
 _dp = ctypes.POINTER(ctypes.c_double)
 

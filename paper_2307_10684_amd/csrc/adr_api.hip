@@ -29,8 +29,7 @@ struct TuckerGroup {
   int count = 0;
   const void* in[kMaxGroup] = {};
   const double* M[kMaxGroup][3] = {};      // FP64 matrices, or FP32 copies (reduced precision)
-  const unsigned short* Mh[kMaxGroup][3] = {};  // split-BF16 parts (BF16X3)
-  const unsigned short* Ml[kMaxGroup][3] = {};
+  SplitPlanes Mp[kMaxGroup][3] = {};        // split-BF16 parts of each matrix
   void* out[kMaxGroup] = {};
   const double* Y[kMaxGroup] = {};
   const float* Z[kMaxGroup] = {};   // reduced precision: FP32 second addend of the last product
@@ -100,22 +99,20 @@ hipError_t run_tucker(const Geometry& g, const TuckerGroup& tg, double alpha, do
                 [&] { return launch_mode_product_f64(a, s); });
     } else {
       const void* Mf[kMaxGroup];
-      const void* Mh[kMaxGroup];
-      const void* Ml[kMaxGroup];
+      SplitPlanes Mp[kMaxGroup];
       const double* Y[kMaxGroup];
       const float* Z[kMaxGroup];
       bool with_z = false;
       for (int k = 0; k < tg.count; ++k) {
         Mf[k] = tg.M[k][mu];
-        Mh[k] = tg.Mh[k][mu];
-        Ml[k] = tg.Ml[k][mu];
+        Mp[k] = tg.Mp[k][mu];
         Y[k] = last ? tg.Y[k] : nullptr;
         Z[k] = last ? tg.Z[k] : nullptr;
         with_z = with_z || Z[k] != nullptr;
       }
       const long long X = g.N / g.n[mu];
       e = timed(with_z ? kKindModeFused : kKindMode, s, [&] {
-        return launch_tgemm_lowp(precision, W, Mf, Mh, Ml, out, Y, tg.count, g.n[mu], X,
+        return launch_tgemm_lowp(precision, W, Mf, Mp, out, Y, tg.count, g.n[mu], X,
                                  last ? alpha : 1.0, last ? beta : 0.0,
                                  (last && !last_f32) ? 1 : 0, s, with_z ? Z : nullptr);
       });
@@ -137,7 +134,7 @@ int check_problem(const adr_problem* p, Geometry& g) {
   if (p->d < 1 || p->d > ADR_MAX_DIM) return ADR_EINVAL;
   if (p->model < ADR_SCHNAKENBERG || p->model > ADR_DIB) return ADR_EINVAL;
   if (p->scheme != ADR_ETD2RKDS && p->scheme != ADR_LAWSON2B) return ADR_EINVAL;
-  if (p->precision < ADR_F64 || p->precision > ADR_BF16X3) return ADR_EINVAL;
+  if (p->precision < ADR_F64 || p->precision > ADR_BF16X2) return ADR_EINVAL;
   if (p->flags != 0) return ADR_EINVAL;
   if (!finite_pos(p->tau)) return ADR_EINVAL;
   for (int i = 0; i < ADR_MAX_PARAMS; ++i)
@@ -197,8 +194,8 @@ Carve carve(const adr_problem* p, const Geometry& g, char* base) {
           if (p->precision == ADR_F32) {
             c.phi32[cc][j][mu] = static_cast<float*>(take(align_up(nn * sizeof(float))));
           } else {
-            c.phih[cc][j][mu] = static_cast<unsigned short*>(take(align_up(nn * 2)));
-            c.phil[cc][j][mu] = static_cast<unsigned short*>(take(align_up(nn * 2)));
+            for (int q = 0; q < split_parts(p->precision); ++q)
+              c.phip[cc][j][mu][q] = static_cast<unsigned short*>(take(align_up(nn * 2)));
           }
         }
   }
@@ -224,8 +221,8 @@ hipError_t prepare_lowp(const adr_problem* p, const Geometry& g, const Carve& c,
         hipError_t e = (p->precision == ADR_F32)
                            ? launch_convert_f64_f32(src, c.phi32[cc][j][mu],
                                                     (size_t)g.n[mu] * g.n[mu], s)
-                           : launch_split_bf16(g.n[mu], src, c.phih[cc][j][mu],
-                                               c.phil[cc][j][mu], s);
+                           : launch_split_bf16(g.n[mu], split_parts(p->precision), src,
+                                               c.phip[cc][j][mu], s);
         if (e != hipSuccess) return e;
       }
   return hipSuccess;
@@ -244,8 +241,7 @@ void set_phi(TuckerGroup& tg, int k, const adr_problem* p, const Carve& c, int c
   } else if (p->precision == ADR_F32) {
     tg.M[k][mu] = reinterpret_cast<const double*>(c.phi32[comp][j][mu]);
   } else {
-    tg.Mh[k][mu] = c.phih[comp][j][mu];
-    tg.Ml[k][mu] = c.phil[comp][j][mu];
+    for (int q = 0; q < 3; ++q) tg.Mp[k][mu].p[q] = c.phip[comp][j][mu][q];
   }
 }
 

@@ -226,7 +226,7 @@ int validate(int count, const adr_problem* probs, double* const* U, double* cons
     const int st = check_problem(p, geoms[i]);
     if (st != ADR_OK) return st;
     if (p->scheme != ADR_ETD2RKDS) return ADR_ENOTSUP;
-    if (p->precision != probs[0].precision || p->precision == ADR_BF16X3) return ADR_ENOTSUP;
+    if (p->precision != probs[0].precision || (p->precision != ADR_F64 && p->precision != ADR_F32)) return ADR_ENOTSUP;
     for (int c = 0; c < 2; ++c)
       for (int mu = 0; mu < p->d; ++mu)
         if (!p->band[c][mu]) return ADR_ENOTSUP;

@@ -73,17 +73,21 @@ hipError_t launch_mode_grouped_f64(TileCfg cfg, bool kfast, const TileJob* jobs,
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_mode_product_f64(const ModeArgs& a, hipStream_t s);
 
-// Reduced-precision "transposing" product (precision 1 = FP32, 2 = split BF16):
+// Reduced-precision "transposing" product (precision kLowpF32, kLowpBF16X3 or
+// kLowpBF16X2, the adr_precision values):
 //   out[x + X*i] = alpha * sum_k M[i,k] W[k + n*x] (+ beta * Y[x + X*i])
-// W: FP32 n x X column-major; M: FP32 n x n column-major (FP32) or transposed
-// bf16 hi/lo parts (BF16X3); out: FP32, or FP64 with the FP64 addend Y.
-// With the FP32 addends Z (FP64 output only):
+// W: FP32 n x X column-major; M: FP32 n x n column-major (FP32) or the split
+// BF16 parts of M as transposed planes (three or two); out: FP32, or FP64 with
+// the FP64 addend Y.  With the FP32 addends Z (FP64 output only):
 //   out = (beta * Y + Z) + alpha * sum_k M[i,k] W[k + n*x].
+constexpr int kLowpF32 = 1, kLowpBF16X3 = 2, kLowpBF16X2 = 3;
+struct SplitPlanes {
+  const unsigned short* p[3];   // the parts, largest first (p[2] unused with two parts)
+};
 hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* const* Mf32,
-                             const void* const* Mh, const void* const* Ml, void* const* out,
-                             const double* const* Y, int group, int n, long long X, double alpha,
-                             double beta, int out_f64, hipStream_t s,
-                             const float* const* Z = nullptr);
+                             const SplitPlanes* Mp, void* const* out, const double* const* Y,
+                             int group, int n, long long X, double alpha, double beta, int out_f64,
+                             hipStream_t s, const float* const* Z = nullptr);
 // One FP32 transposing product of a grouped launch (tiles of 128 x 128).
 struct LowpJob {
   const float* W;
@@ -101,8 +105,10 @@ struct LowpJob {
 // vec: every job has n % 4 == 0 and 16-byte aligned W and M (vectorised loads)
 hipError_t launch_tgemm_lowp_grouped(int precision, const LowpJob* jobs, int njobs,
                                      long long ntiles, bool vec, hipStream_t s);
-// Split an FP64 n x n column-major matrix into transposed bf16 hi/lo parts.
-hipError_t launch_split_bf16(int n, const double* M, unsigned short* Mh, unsigned short* Ml,
+// Split an FP64 n x n column-major matrix into `parts` (2 or 3) transposed bf16
+// planes P[p][i*n + k]: each part is the bf16 rounding of the remainder the
+// previous parts leave.
+hipError_t launch_split_bf16(int n, int parts, const double* M, unsigned short* const* P,
                              hipStream_t s);
 
 struct StageGeom {

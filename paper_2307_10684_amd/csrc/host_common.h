@@ -63,7 +63,10 @@ inline bool mode_geometry(const Geometry& g, int mu, long long& L, long long& R)
 
 // Workspace carve-up.  Tensors are FP64 (8 bytes) or FP32 (4 bytes) for the
 // reduced-precision intermediates; reduced-precision modes also hold FP32
-// copies of the small matrices.
+// copies, or the split-BF16 parts, of the small matrices.
+inline int split_parts(int precision) {
+  return precision == ADR_BF16X3 ? 3 : precision == ADR_BF16X2 ? 2 : 0;
+}
 struct Carve {
   double* U2 = nullptr;
   double* V2 = nullptr;
@@ -71,8 +74,7 @@ struct Carve {
   void* R[4] = {};
   void* T[4] = {};
   float* phi32[2][3][3] = {};            // FP32 copies (ADR_F32)
-  unsigned short* phih[2][3][3] = {};    // split-BF16 parts, transposed (ADR_BF16X3)
-  unsigned short* phil[2][3][3] = {};
+  unsigned short* phip[2][3][3][3] = {};  // split-BF16 parts [comp][j][mu][part], transposed
   size_t bytes = 0;
 };
 

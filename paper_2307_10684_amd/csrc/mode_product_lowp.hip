@@ -3,12 +3,23 @@
 // FP64; only the bulk products run in lower precision):
 //
 //   FP32      v_mfma_f32_16x16x4_f32 on FP32 data;
-//   BF16X3    each FP32 operand x is split as x = hi + lo with hi = bf16(x),
-//             lo = bf16(x - hi), and a*b is taken as hi_a hi_b + hi_a lo_b +
-//             lo_a hi_b on v_mfma_f32_16x16x32_bf16 with FP32 accumulation (the
-//             lo_a lo_b term, ~2^-16 relative, is dropped).
+//   BF16X3    each FP32 operand x is split into three bf16 parts,
+//             x = hi + mid + lo (each part the bf16 rounding of what the
+//             previous ones leave; for an FP32 x the three carry all 24 bits,
+//             so the split is exact), and a*b is taken as the six products
+//             hi_a hi_b + hi_a mid_b + mid_a hi_b + hi_a lo_b + mid_a mid_b +
+//             lo_a hi_b on v_mfma_f32_16x16x32_bf16 with FP32 accumulation;
+//             the dropped terms are below 2^-22 of |a b|.  The instruction
+//             itself adds each group of eight k-products after aligning them
+//             to the largest and drops the bits below its 24-bit precision
+//             (probed on gfx950; its addition of the accumulator rounds to
+//             nearest), so a group sum can lose up to about seven units of
+//             2^-24 of its largest product: the accuracy ends near 2^-21 of
+//             the largest product, not at the FP32 rounding;
+//   BF16X2    two parts, x ~ hi + lo, three products hi hi + hi lo + lo hi
+//             (about 2^-16 relative: a faster, less accurate variant).
 //
-// Both use one "transposing" product form,
+// All use one "transposing" product form,
 //
 //   out[x + X*i] = alpha * sum_k M[i,k] W[k + n*x]  (+ beta * Y[x + X*i]),
 //
@@ -21,6 +32,8 @@
 // Fragment layouts (wave64, probed on gfx950): f32 16x16x4 takes A[l%16][l/16],
 // B[l/16][l%16]; bf16 16x16x32 takes A[l%16][8(l/16)+j], B[8(l/16)+j][l%16],
 // j = 0..7; both return D[4(l/16)+v][l%16], v = 0..3.
+#include <algorithm>
+
 #include "common.h"
 
 namespace adr {
@@ -41,8 +54,8 @@ __device__ __forceinline__ float bf16_float(unsigned short b) {
 struct LowpArgs {
   const float* W[kMaxGroup];     // inputs, n x X column-major (fibres contiguous)
   const float* M[kMaxGroup];     // FP32: n x n column-major
-  const unsigned short* Mh[kMaxGroup];  // BF16X3: transposed hi/lo parts, k fastest
-  const unsigned short* Ml[kMaxGroup];
+  // split BF16: the parts of M (hi, mid, lo) as transposed planes, k fastest
+  const unsigned short* Mp[kMaxGroup][3];
   void* out[kMaxGroup];          // FP32 (rotated) or FP64 (last product)
   const double* Y[kMaxGroup];    // FP64 addend for the last product, may alias out
   const float* Z[kMaxGroup];     // FP32 second addend of the last product, or null
@@ -84,7 +97,8 @@ __device__ __forceinline__ LowpJob job_of(const LowpArgs& a, int g) {
 // the next strip's loads in flight.  Loads use clamped indices (no branches);
 // only stores outside the tensor are masked, and a wave tile that lies wholly
 // inside it skips the masks.
-template <int FI, int FX, bool HASY, bool HASZ, bool GUARD>
+// NBUF = 1 loads each strip's addends just before its stores (fewer registers).
+template <int FI, int FX, bool HASY, bool HASZ, bool GUARD, int NBUF = 2>
 __device__ __forceinline__ void tgemm_epilogue64(const LowpJob& a, const f4 (&acc)[FI][FX], int ib,
                                                  unsigned xb, int col, int krow) {
   const int n = a.n;
@@ -93,8 +107,8 @@ __device__ __forceinline__ void tgemm_epilogue64(const LowpJob& a, const f4 (&ac
   const double* Y = a.Y;
   const float* Z = a.Z;
   double* out = static_cast<double*>(a.out);
-  double y[2][FI][4];
-  float z[2][FI][4];
+  double y[NBUF][FI][4];
+  float z[NBUF][FI][4];
   // outside the tensor the loads read a clamped (valid, lane-varying) element
   auto index = [&](int fx, int fi, int v, bool& ok) {
     unsigned x = xb + fx * 16 + col;
@@ -113,14 +127,15 @@ __device__ __forceinline__ void tgemm_epilogue64(const LowpJob& a, const f4 (&ac
       for (int v = 0; v < 4; ++v) {
         bool ok;
         const unsigned o = index(fx, fi, v, ok);
-        if (HASY) y[fx & 1][fi][v] = Y[o];
-        if (HASZ) z[fx & 1][fi][v] = Z[o];
+        if (HASY) y[fx % NBUF][fi][v] = Y[o];
+        if (HASZ) z[fx % NBUF][fi][v] = Z[o];
       }
   };
-  load_strip(0);
+  if (NBUF == 2) load_strip(0);
 #pragma unroll
   for (int fx = 0; fx < FX; ++fx) {
-    if (fx + 1 < FX) load_strip(fx + 1);
+    if (NBUF == 1) load_strip(fx);
+    else if (fx + 1 < FX) load_strip(fx + 1);
 #pragma unroll
     for (int fi = 0; fi < FI; ++fi)
 #pragma unroll
@@ -129,14 +144,14 @@ __device__ __forceinline__ void tgemm_epilogue64(const LowpJob& a, const f4 (&ac
         const unsigned o = index(fx, fi, v, ok);
         const double p = alpha * (double)acc[fi][fx][v];
         double val = p;
-        if (HASZ) val = ((HASY ? beta * y[fx & 1][fi][v] : 0.0) + (double)z[fx & 1][fi][v]) + p;
-        else if (HASY) val = p + beta * y[fx & 1][fi][v];
+        if (HASZ) val = ((HASY ? beta * y[fx % NBUF][fi][v] : 0.0) + (double)z[fx % NBUF][fi][v]) + p;
+        else if (HASY) val = p + beta * y[fx % NBUF][fi][v];
         if (ok) out[o] = val;
       }
   }
 }
 
-template <int FI, int FX, int TI, int TX, bool OUT64>
+template <int FI, int FX, int TI, int TX, bool OUT64, int NBUF = 2>
 __device__ __forceinline__ void tgemm_epilogue(const LowpJob& a, const f4 (&acc)[FI][FX],
                                                int ib, unsigned xb, int col, int krow) {
   const int n = a.n;
@@ -147,21 +162,21 @@ __device__ __forceinline__ void tgemm_epilogue(const LowpJob& a, const f4 (&acc)
     const bool hy = a.Y != nullptr, hz = a.Z != nullptr;
     if (inside) {
       if (hz) {
-        if (hy) tgemm_epilogue64<FI, FX, true, true, false>(a, acc, ib, xb, col, krow);
-        else tgemm_epilogue64<FI, FX, false, true, false>(a, acc, ib, xb, col, krow);
+        if (hy) tgemm_epilogue64<FI, FX, true, true, false, NBUF>(a, acc, ib, xb, col, krow);
+        else tgemm_epilogue64<FI, FX, false, true, false, NBUF>(a, acc, ib, xb, col, krow);
       } else if (hy) {
-        tgemm_epilogue64<FI, FX, true, false, false>(a, acc, ib, xb, col, krow);
+        tgemm_epilogue64<FI, FX, true, false, false, NBUF>(a, acc, ib, xb, col, krow);
       } else {
-        tgemm_epilogue64<FI, FX, false, false, false>(a, acc, ib, xb, col, krow);
+        tgemm_epilogue64<FI, FX, false, false, false, NBUF>(a, acc, ib, xb, col, krow);
       }
     } else {
       if (hz) {
-        if (hy) tgemm_epilogue64<FI, FX, true, true, true>(a, acc, ib, xb, col, krow);
-        else tgemm_epilogue64<FI, FX, false, true, true>(a, acc, ib, xb, col, krow);
+        if (hy) tgemm_epilogue64<FI, FX, true, true, true, NBUF>(a, acc, ib, xb, col, krow);
+        else tgemm_epilogue64<FI, FX, false, true, true, NBUF>(a, acc, ib, xb, col, krow);
       } else if (hy) {
-        tgemm_epilogue64<FI, FX, true, false, true>(a, acc, ib, xb, col, krow);
+        tgemm_epilogue64<FI, FX, true, false, true, NBUF>(a, acc, ib, xb, col, krow);
       } else {
-        tgemm_epilogue64<FI, FX, false, false, true>(a, acc, ib, xb, col, krow);
+        tgemm_epilogue64<FI, FX, false, false, true, NBUF>(a, acc, ib, xb, col, krow);
       }
     }
     return;
@@ -343,22 +358,61 @@ __global__ __launch_bounds__(kThreads, 2) void k_tgemm_f32_grouped(const LowpJob
 }
 
 // ------------------------------------------------------------------ split BF16
-// Tile: BI rows i x BX fibres, BK = 32 (one bf16 MFMA depth) per chunk.  The W
-// chunk is loaded as FP32 (eight consecutive k per lane), split into hi/lo and
-// stored k-fastest; M arrives pre-split and transposed (k fastest).
-template <int BI, int BX, bool OUT64, bool FULL, int PADB = 0, int WI = 2, int WX = 2>
-__global__ __launch_bounds__(64 * WI * WX, 2) void k_tgemm_bf16x3(LowpArgs a, int n_itiles,
-                                                                 int n_xtiles) {
+// Split of one FP32 value into PARTS bf16 parts: each part is the bf16
+// rounding (to nearest even) of what the previous parts leave.  The
+// remainders are exact FP32 differences; with three parts the last one is
+// exactly representable, so hi + mid + lo == x.
+template <int PARTS>
+__device__ __forceinline__ void split_bf16(float x, unsigned short (&part)[PARTS]) {
+  float r = x;
+#pragma unroll
+  for (int p = 0; p < PARTS; ++p) {
+    part[p] = bf16_bits(r);
+    if (p + 1 < PARTS) r = r - bf16_float(part[p]);
+  }
+}
+
+// One 16x16 block of the split product over a 32-deep chunk: the products of
+// parts (pa, pb) with pa + pb < PARTS, the smallest first.
+template <int PARTS>
+__device__ __forceinline__ f4 split_mfma(const s8 (&a)[PARTS], const s8 (&b)[PARTS], f4 acc) {
+  if constexpr (PARTS == 3) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], acc, 0, 0, 0);
+  } else {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], acc, 0, 0, 0);
+  }
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], acc, 0, 0, 0);
+}
+
+// Generic tiles: BI rows i x BX fibres, BK = 32 (one bf16 MFMA depth) per
+// chunk, one tile per workgroup, bounds-checked unless FULL.  The W chunk is
+// loaded as FP32 (eight consecutive k per lane), split and stored k-fastest;
+// M arrives pre-split and transposed (k fastest).  Each LDS row holds 32 bf16
+// (four 16-byte quads) and quad q of row r sits in slot q ^ ((r >> 1) & 3),
+// so the rows of a fragment read spread over the banks.  NBUF = 2: two chunk
+// buffers, one barrier per chunk; NBUF = 1: one buffer (the chunk after next
+// waits in registers), two barriers per chunk, and half the LDS, so that more
+// workgroups share a CU and overlap each other's phases.
+template <int BI, int BX, bool OUT64, bool FULL, int PARTS, int NBUF = 2, int WI = 2, int WX = 2>
+__global__ __launch_bounds__(64 * WI * WX, 2) void k_tgemm_bf16s(LowpArgs a, int n_itiles,
+                                                                int n_xtiles) {
   constexpr int BK = 32;
   constexpr int kThreads = 64 * WI * WX;
   constexpr int TI = BI / WI, TX = BX / WX, FI = TI / 16, FX = TX / 16;
-  constexpr int LDK = BK + PADB;            // bf16 elements per row (16-byte aligned pitch)
+  constexpr int LDK = BK;                    // bf16 elements per row
   constexpr int MSEG = BI * (BK / 8);        // 8-element segments of the M chunk
   constexpr int WSEG = BX * (BK / 8);
   constexpr int MLOADS = MSEG / kThreads, WLOADS = WSEG / kThreads;
   static_assert(MLOADS * kThreads == MSEG && WLOADS * kThreads == WSEG, "mapping");
-  __shared__ unsigned short sMh[2][BI * LDK], sMl[2][BI * LDK];
-  __shared__ unsigned short sWh[2][BX * LDK], sWl[2][BX * LDK];
+  static_assert(TI % 16 == 0 && TX % 16 == 0, "fragment rows keep their low four bits");
+  __shared__ unsigned short sM[NBUF][PARTS][BI * LDK];
+  __shared__ unsigned short sW[NBUF][PARTS][BX * LDK];
+  auto slot = [](int r, int q) { return 8 * (q ^ ((r >> 1) & 3)); };
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = wave / WX, wx = wave % WX;
@@ -373,28 +427,27 @@ __global__ __launch_bounds__(64 * WI * WX, 2) void k_tgemm_bf16x3(LowpArgs a, in
   const int i0 = itile * BI;
   const unsigned x0 = (unsigned)xtile * BX;
   const float* __restrict__ W = a.W[g];
-  const unsigned short* __restrict__ Mh = a.Mh[g];
-  const unsigned short* __restrict__ Ml = a.Ml[g];
 
   // segment s of a chunk: row r = s / 4 (i or x), k-group q = s % 4 (8 k-values)
-  s8 rmh[MLOADS], rml[MLOADS];
+  s8 rm[MLOADS][PARTS];
   float rw[WLOADS][8];
   auto load = [&](int k0) {
 #pragma unroll
     for (int p = 0; p < MLOADS; ++p) {
       const int s = tid + p * kThreads, r = s >> 2, q = s & 3;
       const int i = i0 + r, k = k0 + 8 * q;
-      if (FULL) {  // whole tile in range, 16-byte aligned rows
-        const unsigned idx = (unsigned)i * (unsigned)n + (unsigned)k;
-        rmh[p] = *reinterpret_cast<const s8*>(Mh + idx);
-        rml[p] = *reinterpret_cast<const s8*>(Ml + idx);
-      } else {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const bool ok = i < n && (k + j) < n;
-          const unsigned idx = ok ? (unsigned)i * (unsigned)n + (unsigned)(k + j) : 0u;
-          rmh[p][j] = ok ? (short)Mh[idx] : (short)0;
-          rml[p][j] = ok ? (short)Ml[idx] : (short)0;
+      for (int pp = 0; pp < PARTS; ++pp) {
+        const unsigned short* __restrict__ Mp = a.Mp[g][pp];
+        if (FULL) {  // whole tile in range, 16-byte aligned rows
+          rm[p][pp] = *reinterpret_cast<const s8*>(Mp + (unsigned)i * (unsigned)n + (unsigned)k);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const bool ok = i < n && (k + j) < n;
+            const unsigned idx = ok ? (unsigned)i * (unsigned)n + (unsigned)(k + j) : 0u;
+            rm[p][pp][j] = ok ? (short)Mp[idx] : (short)0;
+          }
         }
       }
     }
@@ -424,21 +477,24 @@ __global__ __launch_bounds__(64 * WI * WX, 2) void k_tgemm_bf16x3(LowpArgs a, in
 #pragma unroll
     for (int p = 0; p < MLOADS; ++p) {
       const int s = tid + p * kThreads, r = s >> 2, q = s & 3;
-      *reinterpret_cast<s8*>(&sMh[buf][r * LDK + 8 * q]) = rmh[p];
-      *reinterpret_cast<s8*>(&sMl[buf][r * LDK + 8 * q]) = rml[p];
+#pragma unroll
+      for (int pp = 0; pp < PARTS; ++pp)
+        *reinterpret_cast<s8*>(&sM[buf][pp][r * LDK + slot(r, q)]) = rm[p][pp];
     }
 #pragma unroll
     for (int p = 0; p < WLOADS; ++p) {
       const int s = tid + p * kThreads, r = s >> 2, q = s & 3;
-      s8 h, l;
+      s8 v[PARTS];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        const unsigned short hb = bf16_bits(rw[p][j]);
-        h[j] = (short)hb;
-        l[j] = (short)bf16_bits(rw[p][j] - bf16_float(hb));
+        unsigned short part[PARTS];
+        split_bf16<PARTS>(rw[p][j], part);
+#pragma unroll
+        for (int pp = 0; pp < PARTS; ++pp) v[pp][j] = (short)part[pp];
       }
-      *reinterpret_cast<s8*>(&sWh[buf][r * LDK + 8 * q]) = h;
-      *reinterpret_cast<s8*>(&sWl[buf][r * LDK + 8 * q]) = l;
+#pragma unroll
+      for (int pp = 0; pp < PARTS; ++pp)
+        *reinterpret_cast<s8*>(&sW[buf][pp][r * LDK + slot(r, q)]) = v[pp];
     }
   };
 
@@ -452,50 +508,205 @@ __global__ __launch_bounds__(64 * WI * WX, 2) void k_tgemm_bf16x3(LowpArgs a, in
   store(0);
   __syncthreads();
   const int col = lane & 15, kq = lane >> 4;
+  const int frag = slot(col, kq);   // the rows read below keep col as their low four bits
   for (int c = 0; c < nchunks; ++c) {
-    const int buf = c & 1;
+    const int buf = NBUF == 2 ? (c & 1) : 0;
     if (c + 1 < nchunks) load((c + 1) * BK);
-    s8 ah[FI], al[FI], bh[FX], bl[FX];
+    s8 af[FI][PARTS];
 #pragma unroll
     for (int fi = 0; fi < FI; ++fi) {
       const int r = wi * TI + fi * 16 + col;
-      ah[fi] = *reinterpret_cast<const s8*>(&sMh[buf][r * LDK + 8 * kq]);
-      al[fi] = *reinterpret_cast<const s8*>(&sMl[buf][r * LDK + 8 * kq]);
+#pragma unroll
+      for (int pp = 0; pp < PARTS; ++pp)
+        af[fi][pp] = *reinterpret_cast<const s8*>(&sM[buf][pp][r * LDK + frag]);
     }
 #pragma unroll
     for (int fx = 0; fx < FX; ++fx) {
       const int r = wx * TX + fx * 16 + col;
-      bh[fx] = *reinterpret_cast<const s8*>(&sWh[buf][r * LDK + 8 * kq]);
-      bl[fx] = *reinterpret_cast<const s8*>(&sWl[buf][r * LDK + 8 * kq]);
+      s8 bf[PARTS];
+#pragma unroll
+      for (int pp = 0; pp < PARTS; ++pp)
+        bf[pp] = *reinterpret_cast<const s8*>(&sW[buf][pp][r * LDK + frag]);
+#pragma unroll
+      for (int fi = 0; fi < FI; ++fi) acc[fi][fx] = split_mfma<PARTS>(af[fi], bf, acc[fi][fx]);
     }
-#pragma unroll
-    for (int fi = 0; fi < FI; ++fi)
-#pragma unroll
-      for (int fx = 0; fx < FX; ++fx) {
-        // small terms first, the dominant product last
-        acc[fi][fx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[fi], bh[fx], acc[fi][fx], 0, 0, 0);
-        acc[fi][fx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[fi], bl[fx], acc[fi][fx], 0, 0, 0);
-        acc[fi][fx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[fi], bh[fx], acc[fi][fx], 0, 0, 0);
-      }
-    if (c + 1 < nchunks) store(buf ^ 1);
+    if (NBUF == 1) __syncthreads();   // every wave is done with the buffer
+    if (c + 1 < nchunks) store(NBUF == 2 ? (buf ^ 1) : 0);
     __syncthreads();
   }
   tgemm_epilogue<FI, FX, TI, TX, OUT64>(job_of(a, g), acc, i0 + wi * TI, x0 + wx * TX, col, kq);
 }
 
-// Split an FP64 n x n column-major matrix into transposed bf16 hi/lo parts:
-// Mh[i*n + k] + Ml[i*n + k] ~ M[i + n*k] (via FP32).
-__global__ __launch_bounds__(256) void k_split_bf16(int n, const double* __restrict__ M,
-                                                    unsigned short* __restrict__ Mh,
-                                                    unsigned short* __restrict__ Ml) {
+// Wide tiles for evenly tiled shapes (n % 256 == 0, X % 128 == 0): 256 rows x
+// 128 fibres per workgroup, eight waves in a 4 x 2 grid of 64 x 64 wave
+// tiles, one workgroup per CU walking the tiles of the launch (persistent:
+// tile b, b + G, ...).  Two chunk buffers of PARTS bf16 planes each (three
+// parts: 96 KB of M, 48 KB of W).  The M planes arrive pre-split and go from
+// global memory straight into LDS (global_load_lds, lane l writing bytes
+// 16 l onward of the wave's 1 KB span); W arrives as FP32, is split in
+// registers and stored.  Each LDS row holds 32 bf16 (four 16-byte quads), and
+// quad q of row r sits in slot q ^ ((r >> 1) & 3): the eight rows a fragment
+// read puts in one 128-byte bank window then use all eight 16-byte slots.
+// The next chunk (of this tile, or the first of the next) is in flight while
+// the current one is multiplied; the two buffers are distinct LDS objects and
+// the chunk loop is unrolled by two, so the loads into one buffer are waited
+// for only at the barrier.
+template <int PARTS, bool OUT64>
+__global__ __launch_bounds__(512, 1) void k_tgemm_bf16s_wide(LowpArgs a, int n_itiles,
+                                                            int n_xtiles, int ntiles) {
+  constexpr int BI = 256, BX = 128, BK = 32, WX = 2;
+  constexpr int TI = 64, TX = 64, FI = TI / 16, FX = TX / 16;
+  constexpr int PLANE_M = BI * BK, PLANE_W = BX * BK;   // bf16 elements per plane
+  __shared__ __attribute__((aligned(16))) unsigned short sM0[PARTS * PLANE_M];
+  __shared__ __attribute__((aligned(16))) unsigned short sM1[PARTS * PLANE_M];
+  __shared__ __attribute__((aligned(16))) unsigned short sW0[PARTS * PLANE_W];
+  __shared__ __attribute__((aligned(16))) unsigned short sW1[PARTS * PLANE_W];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave / WX, wx = wave % WX;
+  const int n = a.n;
+  const int nchunks = n / BK;              // even: n % 256 == 0
+  const int G = gridDim.x;
+
+  struct Tile {
+    int g, i0;
+    unsigned x0;
+  };
+  auto tile_of = [&](int t) {
+    Tile T;
+    T.i0 = (t % n_itiles) * BI;
+    t /= n_itiles;
+    T.x0 = (unsigned)(t % n_xtiles) * BX;
+    T.g = t / n_xtiles;
+    return T;
+  };
+
+  // M chunk: per part 256 rows x 64 bytes = 16 spans of 1 KB (16 rows each); wave
+  // w fills rows 32 w .. 32 w + 31.  Lane l of a span fills row R0 + l / 4, slot
+  // l % 4, with the quad that the slot holds.
+  const int dma_r = lane >> 2, dma_slot = lane & 3;
+  auto dma_m = [&](unsigned short* dst, const Tile& T, int k0) {
+#pragma unroll
+    for (int pp = 0; pp < PARTS; ++pp) {
+      const unsigned short* __restrict__ Mp = a.Mp[T.g][pp];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int R0 = 32 * wave + 16 * h;
+        const int r = R0 + dma_r;
+        const int q = dma_slot ^ ((r >> 1) & 3);
+        const unsigned src = (unsigned)(T.i0 + r) * (unsigned)n + (unsigned)(k0 + 8 * q);
+        __builtin_amdgcn_global_load_lds(Mp + src, dst + pp * PLANE_M + R0 * BK, 16, 0, 0);
+      }
+    }
+  };
+  // W chunk: 128 fibres x 32 k FP32; thread t takes fibre t / 4, k-quad t % 4
+  const int w_x = tid >> 2, w_q = tid & 3;
+  const int w_slot = w_q ^ ((w_x >> 1) & 3);
+  f4 rw0, rw1;
+  auto load_w = [&](const Tile& T, int k0) {
+    const f4* src = reinterpret_cast<const f4*>(a.W[T.g] + (T.x0 + (unsigned)w_x) * (unsigned)n +
+                                                (unsigned)(k0 + 8 * w_q));
+    rw0 = src[0];
+    rw1 = src[1];
+  };
+  auto store_w = [&](unsigned short* dst) {
+    s8 v[PARTS];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      unsigned short part[PARTS];
+      split_bf16<PARTS>(j < 4 ? rw0[j] : rw1[j - 4], part);
+#pragma unroll
+      for (int pp = 0; pp < PARTS; ++pp) v[pp][j] = (short)part[pp];
+    }
+#pragma unroll
+    for (int pp = 0; pp < PARTS; ++pp)
+      *reinterpret_cast<s8*>(dst + pp * PLANE_W + w_x * BK + 8 * w_slot) = v[pp];
+  };
+
+  // fragment reads: row r (low four bits = lane % 16), quad lane / 16
+  const int col = lane & 15, kq = lane >> 4;
+  const int frag_off = 8 * (kq ^ ((col >> 1) & 3));
+  f4 acc[FI][FX];
+  auto compute = [&](const unsigned short* cm, const unsigned short* cw) {
+    s8 af[FI][PARTS];
+#pragma unroll
+    for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+      for (int pp = 0; pp < PARTS; ++pp)
+        af[fi][pp] = *reinterpret_cast<const s8*>(cm + pp * PLANE_M +
+                                                  (wi * TI + fi * 16 + col) * BK + frag_off);
+#pragma unroll
+    for (int fx = 0; fx < FX; ++fx) {
+      s8 bf[PARTS];
+#pragma unroll
+      for (int pp = 0; pp < PARTS; ++pp)
+        bf[pp] = *reinterpret_cast<const s8*>(cw + pp * PLANE_W +
+                                              (wx * TX + fx * 16 + col) * BK + frag_off);
+#pragma unroll
+      for (int fi = 0; fi < FI; ++fi) acc[fi][fx] = split_mfma<PARTS>(af[fi], bf, acc[fi][fx]);
+    }
+  };
+
+  int t = blockIdx.x;
+  if (t >= ntiles) return;
+  Tile cur = tile_of(t);
+  dma_m(sM0, cur, 0);
+  load_w(cur, 0);
+  store_w(sW0);
+  __syncthreads();
+  while (true) {
+    const int tn = t + G;
+    const bool next_tile = tn < ntiles;
+    const Tile nxt = tile_of(next_tile ? tn : t);
+#pragma unroll
+    for (int fi = 0; fi < FI; ++fi)
+#pragma unroll
+      for (int fx = 0; fx < FX; ++fx) acc[fi][fx] = f4{0.f, 0.f, 0.f, 0.f};
+    // chunk c from (cm, cw); the next chunk goes into (nm, nw)
+    auto step = [&](int c, const unsigned short* cm, const unsigned short* cw, unsigned short* nm,
+                    unsigned short* nw) {
+      const bool in_tile = c + 1 < nchunks;
+      const bool more = in_tile || next_tile;
+      if (more) {
+        const Tile& T = in_tile ? cur : nxt;
+        const int k0 = in_tile ? (c + 1) * BK : 0;
+        dma_m(nm, T, k0);
+        load_w(T, k0);
+      }
+      compute(cm, cw);
+      if (more) store_w(nw);
+      __syncthreads();   // the next chunk has landed and nobody reads (cm, cw) any more
+    };
+    for (int c = 0; c < nchunks; c += 2) {
+      step(c, sM0, sW0, sM1, sW1);
+      step(c + 1, sM1, sW1, sM0, sW0);
+    }
+    tgemm_epilogue<FI, FX, TI, TX, OUT64, 1>(job_of(a, cur.g), acc, cur.i0 + wi * TI,
+                                             cur.x0 + wx * TX, col, kq);
+    if (!next_tile) break;
+    t = tn;
+    cur = nxt;
+  }
+}
+
+// Split an FP64 n x n column-major matrix into PARTS transposed bf16 planes,
+// P[p][i*n + k], with sum_p P[p][i*n + k] ~ M[i + n*k]: each part is the bf16
+// rounding of the FP64 remainder the previous parts leave.
+__global__ __launch_bounds__(256) void k_split_bf16(int n, int parts, const double* __restrict__ M,
+                                                    unsigned short* __restrict__ P0,
+                                                    unsigned short* __restrict__ P1,
+                                                    unsigned short* __restrict__ P2) {
   const long long nn = (long long)n * n;
+  unsigned short* const P[3] = {P0, P1, P2};
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < nn;
        q += (long long)gridDim.x * blockDim.x) {
     const long long i = q / n, k = q % n;   // q = i*n + k
-    const float x = (float)M[i + (long long)n * k];
-    const unsigned short h = bf16_bits(x);
-    Mh[q] = h;
-    Ml[q] = bf16_bits(x - bf16_float(h));
+    double r = M[i + (long long)n * k];
+    for (int p = 0; p < parts; ++p) {
+      const unsigned short h = bf16_bits((float)r);
+      P[p][q] = h;
+      r -= (double)bf16_float(h);
+    }
   }
 }
 
@@ -524,18 +735,20 @@ hipError_t launch_tiles(K kern, const LowpArgs& a, int BI, int BX, hipStream_t s
 }  // namespace
 
 hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* const* Mf32,
-                             const void* const* Mh, const void* const* Ml, void* const* out,
-                             const double* const* Y, int group, int n, long long X, double alpha,
-                             double beta, int out_f64, hipStream_t s, const float* const* Z) {
+                             const SplitPlanes* Mp, void* const* out, const double* const* Y,
+                             int group, int n, long long X, double alpha, double beta, int out_f64,
+                             hipStream_t s, const float* const* Z) {
   if (group < 1 || group > kMaxGroup || X <= 0 || X >= (1LL << 31) ||
       (long long)n * X >= (1LL << 31) || (Z && !out_f64))
     return hipErrorInvalidValue;
+  const int parts = precision == kLowpBF16X3 ? 3 : precision == kLowpBF16X2 ? 2 : 0;
+  if (precision != kLowpF32 && parts == 0) return hipErrorInvalidValue;
+  if (parts && !Mp) return hipErrorInvalidValue;
   LowpArgs a{};
   for (int g = 0; g < group; ++g) {
     a.W[g] = static_cast<const float*>(W[g]);
     a.M[g] = Mf32 ? static_cast<const float*>(Mf32[g]) : nullptr;
-    a.Mh[g] = Mh ? static_cast<const unsigned short*>(Mh[g]) : nullptr;
-    a.Ml[g] = Ml ? static_cast<const unsigned short*>(Ml[g]) : nullptr;
+    for (int p = 0; p < 3; ++p) a.Mp[g][p] = (parts && p < parts) ? Mp[g].p[p] : nullptr;
     a.out[g] = out[g];
     a.Y[g] = Y ? Y[g] : nullptr;
     a.Z[g] = Z ? Z[g] : nullptr;
@@ -551,7 +764,7 @@ hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* co
   // 2048 tiles, 128 rows stay ahead: 185 / 82 against 197 / 89)
   const long long tiles128 = (long long)group * ((n + 127) / 128) * ((X + 127) / 128);
   const bool rows64 = n <= 64 || (n % 128 != 0 && n % 64 == 0) || tiles128 < 2LL * lowp_cu_count();
-  if (precision == 1) {
+  if (precision == kLowpF32) {
     // n % 4 == 0 with 16-byte aligned operands: four floats per lane per load
     bool vec = n % 4 == 0;
     for (int g = 0; g < group; ++g)
@@ -570,26 +783,53 @@ hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* co
     return out_f64 ? launch_tiles(k_tgemm_f32<128, 128, true, false>, a, 128, 128, s)
                    : launch_tiles(k_tgemm_f32<128, 128, false, false>, a, 128, 128, s);
   }
-  // evenly tiled shapes with 16-byte aligned fibres take the vectorised loads
+  // evenly tiled shapes with 16-byte aligned fibres and planes take the vectorised loads
   bool aligned = true;
-  for (int g = 0; g < group; ++g)
-    aligned = aligned && (reinterpret_cast<uintptr_t>(W[g]) % 16 == 0) &&
-              (reinterpret_cast<uintptr_t>(Mh[g]) % 16 == 0) &&
-              (reinterpret_cast<uintptr_t>(Ml[g]) % 16 == 0);
-  if (rows64) {
-    const bool full = aligned && n % 64 == 0 && X % 128 == 0;
-    if (full)
-      return out_f64 ? launch_tiles(k_tgemm_bf16x3<64, 128, true, true>, a, 64, 128, s)
-                     : launch_tiles(k_tgemm_bf16x3<64, 128, false, true>, a, 64, 128, s);
-    return out_f64 ? launch_tiles(k_tgemm_bf16x3<64, 128, true, false>, a, 64, 128, s)
-                   : launch_tiles(k_tgemm_bf16x3<64, 128, false, false>, a, 64, 128, s);
+  for (int g = 0; g < group; ++g) {
+    aligned = aligned && (reinterpret_cast<uintptr_t>(W[g]) % 16 == 0);
+    for (int p = 0; p < parts; ++p)
+      aligned = aligned && (reinterpret_cast<uintptr_t>(Mp[g].p[p]) % 16 == 0);
   }
-  const bool full = aligned && n % 128 == 0 && X % 128 == 0;
-  if (full)
-    return out_f64 ? launch_tiles(k_tgemm_bf16x3<128, 128, true, true>, a, 128, 128, s)
-                   : launch_tiles(k_tgemm_bf16x3<128, 128, false, true>, a, 128, 128, s);
-  return out_f64 ? launch_tiles(k_tgemm_bf16x3<128, 128, true, false>, a, 128, 128, s)
-                 : launch_tiles(k_tgemm_bf16x3<128, 128, false, false>, a, 128, 128, s);
+  // evenly tiled by 256 rows, three parts: the wide persistent tiles, one
+  // workgroup per CU (measured at 256^3: 109 us against 116 us for the
+  // single-buffered 128 x 128 tiles below)
+  if (parts == 3 && aligned && n % 256 == 0 && X % 128 == 0) {
+    const long long ntiles = (long long)group * (n / 256) * (X / 128);
+    if (ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int grid = (int)std::min<long long>(ntiles, lowp_cu_count());
+    const int n_itiles = n / 256, n_xtiles = (int)(X / 128);
+    if (out_f64)
+      hipLaunchKernelGGL((k_tgemm_bf16s_wide<3, true>), dim3(grid), dim3(512), 0, s, a, n_itiles,
+                         n_xtiles, (int)ntiles);
+    else
+      hipLaunchKernelGGL((k_tgemm_bf16s_wide<3, false>), dim3(grid), dim3(512), 0, s, a, n_itiles,
+                         n_xtiles, (int)ntiles);
+    return hipGetLastError();
+  }
+  // evenly tiled by 128 with enough tiles: 128 x 128 tiles with one LDS buffer,
+  // two workgroups per CU (two parts at 256^3: 84.6 us against 91.1 us for the
+  // wide tiles)
+  if (aligned && n % 128 == 0 && X % 128 == 0 && !rows64) {
+    if (parts == 3)
+      return out_f64 ? launch_tiles(k_tgemm_bf16s<128, 128, true, true, 3, 1>, a, 128, 128, s)
+                     : launch_tiles(k_tgemm_bf16s<128, 128, false, true, 3, 1>, a, 128, 128, s);
+    return out_f64 ? launch_tiles(k_tgemm_bf16s<128, 128, true, true, 2, 1>, a, 128, 128, s)
+                   : launch_tiles(k_tgemm_bf16s<128, 128, false, true, 2, 1>, a, 128, 128, s);
+  }
+  // three parts take 64-row tiles (two workgroups per CU fit in LDS)
+  if (rows64 || parts == 3) {
+    const bool full = aligned && n % 64 == 0 && X % 128 == 0;
+#define ADR_BF16S_64(P)                                                                          \
+  (full ? (out_f64 ? launch_tiles(k_tgemm_bf16s<64, 128, true, true, P>, a, 64, 128, s)          \
+                   : launch_tiles(k_tgemm_bf16s<64, 128, false, true, P>, a, 64, 128, s))        \
+        : (out_f64 ? launch_tiles(k_tgemm_bf16s<64, 128, true, false, P>, a, 64, 128, s)         \
+                   : launch_tiles(k_tgemm_bf16s<64, 128, false, false, P>, a, 64, 128, s)))
+    return parts == 3 ? ADR_BF16S_64(3) : ADR_BF16S_64(2);
+#undef ADR_BF16S_64
+  }
+  // ragged 128-row tiles (two parts), bounds-checked
+  return out_f64 ? launch_tiles(k_tgemm_bf16s<128, 128, true, false, 2>, a, 128, 128, s)
+                 : launch_tiles(k_tgemm_bf16s<128, 128, false, false, 2>, a, 128, 128, s);
 }
 
 hipError_t launch_tgemm_lowp_grouped(int precision, const LowpJob* jobs, int njobs,
@@ -605,11 +845,13 @@ hipError_t launch_tgemm_lowp_grouped(int precision, const LowpJob* jobs, int njo
   return hipGetLastError();
 }
 
-hipError_t launch_split_bf16(int n, const double* M, unsigned short* Mh, unsigned short* Ml,
+hipError_t launch_split_bf16(int n, int parts, const double* M, unsigned short* const* P,
                              hipStream_t s) {
+  if (parts < 2 || parts > 3) return hipErrorInvalidValue;
   long long blocks = ((long long)n * n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)blocks), dim3(256), 0, s, n, M, Mh, Ml);
+  hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)blocks), dim3(256), 0, s, n, parts, M, P[0], P[1],
+                     parts == 3 ? P[2] : nullptr);
   return hipGetLastError();
 }
 

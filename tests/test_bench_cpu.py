@@ -50,6 +50,7 @@ def test_source_hash_ignores_comments_and_blank_lines(tmp_path, monkeypatch):
 
 @pytest.mark.parametrize("precision,workload", [
     ("f64", "brusselator3d_256"), ("f32", "brusselator3d_256"), ("bf16x3", "brusselator3d_256"),
+    ("bf16x2", "brusselator3d_256"),
     ("f64", "fhn3d_128"), ("f64", "schnakenberg2d_64")])
 def test_committed_counter_summaries_match_the_kernel_sources(precision, workload):
     # a summary taken before the kernel's code last changed is ignored by bench.py
@@ -78,16 +79,18 @@ def test_cpu_baseline_record():
 
 
 def test_reduced_precision_roofline_bounds():
-    # FP32: the FP32 matrix rate; split BF16 with three products at n = 256: the
-    # matrix cores' time (3 x 2n flops at 2.5 PFLOP/s) is below the time to move
-    # the FP32 operands, so HBM bounds it
+    # FP32: the FP32 matrix rate.  Split BF16 at n = 256: six products (three
+    # parts) take 6 x 2n flops at 2.5 PFLOP/s, longer than moving the FP32
+    # operands at 8 TB/s, so the matrix cores bound it (at 2500/6 TFLOP/s of
+    # FP32-equivalent work); three products (two parts) take less time than the
+    # operands' traffic, so HBM bounds them
     w = S.brusselator_3d()
     r32 = bench._lowp_roofline("f32", w, 0.160, 100, None)
     assert r32["bound"] == "mfma" and r32["peak"] == bench.PEAKS["f32_mfma_tflops"]
     assert abs(r32["achieved"] - 17.179869184e9 / 0.160e-3 / 1e12) < 1e-9
     r3 = bench._lowp_roofline("bf16x3", w, 0.085, 100, None)
-    parts = bench.SPLIT_PRODUCTS["bf16x3"]
-    t_mfma = parts * 17.179869184e9 / 2.5e15
-    t_hbm = 4 * 4 * w.N / 8e12
-    assert r3["bound"] == ("mfma" if t_mfma >= t_hbm else "hbm")
-    assert 0 < r3["frac"] < 1
+    assert r3["bound"] == "mfma" and abs(r3["peak"] - 2500.0 / 6) < 1e-9
+    assert abs(r3["frac"] - 17.179869184e9 / 0.085e-3 / 1e12 / (2500.0 / 6)) < 1e-9
+    r2 = bench._lowp_roofline("bf16x2", w, 0.085, 100, None)
+    assert r2["bound"] == "hbm" and r2["peak"] == bench.PEAKS["hbm_gbs"]
+    assert 0 < r2["frac"] < 1
