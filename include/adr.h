@@ -119,6 +119,24 @@ int adr_precompute_phi(int n, const double* A_dev, double tau, double* E_dev,
                        double* P1_dev, double* P2_dev, void* stream);
 
 /*
+ * adr_precompute_phi_noalloc -- adr_precompute_phi for callers that cannot
+ * allocate device memory (tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same results, worked out in a fixed
+ * array that the library keeps in each GPU's memory until the process ends
+ * (14 n^2 + 1 doubles for n = ADR_PHI_NOALLOC_MAX_N: 29.4 MB per GPU).  It
+ * calls no hipMalloc or hipFree.
+ *   n        1 <= n <= ADR_PHI_NOALLOC_MAX_N; a larger n returns ADR_ENOMEM
+ *            (the fixed array is too small) before any device work
+ * Other arguments and errors as adr_precompute_phi.  All calls on a GPU share
+ * its array, which keeps the last call's contents: calls are serialised by a
+ * lock, and each synchronises `stream` twice (the 1-norm read-back, and before
+ * returning), so no two calls use the array at once.
+ */
+#define ADR_PHI_NOALLOC_MAX_N 512
+int adr_precompute_phi_noalloc(int n, const double* A_dev, double tau, double* E_dev,
+                               double* P1_dev, double* P2_dev, void* stream);
+
+/*
  * One problem instance: grid, model, scheme, and the device-resident small
  * matrices.  The tensors U, V are passed separately to adr_step/adr_solve.
  */

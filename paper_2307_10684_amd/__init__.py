@@ -28,6 +28,7 @@ ADR_ETD2RKDS, ADR_LAWSON2B = 0, 1
 ADR_F64, ADR_F32, ADR_BF16X3, ADR_BF16X2 = 0, 1, 2, 3
 ADR_SCHNAKENBERG, ADR_FHN, ADR_BRUSSELATOR, ADR_ZERO, ADR_DIB = 0, 1, 2, 3, 4
 ADR_MAX_PARAMS = 12
+ADR_PHI_NOALLOC_MAX_N = 512
 ADR_BATCH_AUTOTUNE, ADR_BATCH_GRAPH, ADR_BATCH_PREPARED = 1, 2, 4
 
 
@@ -79,6 +80,7 @@ def _load():
         "adr_version": (c_int, []),
         "adr_build_1d_ops": (c_int, [c_int, c_double, c_double, c_double, c_double, c_int, c_void, c_void]),
         "adr_precompute_phi": (c_int, [c_int, c_void, c_double, c_void, c_void, c_void, c_void]),
+        "adr_precompute_phi_noalloc": (c_int, [c_int, c_void, c_double, c_void, c_void, c_void, c_void]),
         "adr_workspace_bytes": (c_size, [ctypes.POINTER(AdrProblem)]),
         "adr_step": (c_int, [ctypes.POINTER(AdrProblem), c_void, c_void, c_void, c_size, c_void]),
         "adr_solve": (c_int, [ctypes.POINTER(AdrProblem), c_void, c_void, c_int, c_void, c_size, c_void]),
@@ -112,6 +114,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("adr_strerror", "adr_version", "adr_build_1d_ops", "adr_precompute_phi",
+            "adr_precompute_phi_noalloc",
             "adr_workspace_bytes", "adr_step", "adr_solve", "adr_mode_product",
             "adr_tucker_workspace_bytes", "adr_tucker", "adr_device_copy",
             "adr_timing_enable", "adr_timing_read", "adr_indicators_workspace_bytes",
@@ -183,6 +186,24 @@ def adr_precompute_phi(A_dev: torch.Tensor, tau: float, E=None, P1=None, P2=None
         outs.append(t)
     _check(_lib.adr_precompute_phi(n, _ptr(A_dev), float(tau), _ptr(outs[0]), _ptr(outs[1]),
                                    _ptr(outs[2]), _stream(stream)), "adr_precompute_phi")
+    return tuple(outs)
+
+
+def adr_precompute_phi_noalloc(A_dev: torch.Tensor, tau: float, E=None, P1=None, P2=None,
+                               stream=None, want=(True, True, True)):
+    """adr_precompute_phi in the library's fixed per-GPU work area (no device
+    allocation inside the call; n <= ADR_PHI_NOALLOC_MAX_N).  Outputs that are
+    not given are allocated here, before the call."""
+    n = int(round(math.sqrt(A_dev.numel())))
+    _f64_cuda(A_dev, "A_dev")
+    outs = []
+    for t, w in zip((E, P1, P2), want):
+        if t is None and w:
+            t = torch.empty(n * n, dtype=torch.float64, device=A_dev.device)
+        outs.append(t)
+    _check(_lib.adr_precompute_phi_noalloc(n, _ptr(A_dev), float(tau), _ptr(outs[0]),
+                                           _ptr(outs[1]), _ptr(outs[2]), _stream(stream)),
+           "adr_precompute_phi_noalloc")
     return tuple(outs)
 
 

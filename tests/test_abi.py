@@ -130,6 +130,13 @@ def test_other_entry_points_validate(adr):
     assert lib.adr_precompute_phi(8, None, 1e-3, 4096, None, None, None) == adr.ADR_EINVAL
     assert lib.adr_precompute_phi(8, 4096, float("nan"), 4096, None, None, None) == adr.ADR_EINVAL
     assert lib.adr_precompute_phi(8, 4096, 1e-3, None, None, None, None) == adr.ADR_EINVAL
+    # the no-allocation variant: same checks, and sizes beyond its fixed work area
+    nmax = adr.ADR_PHI_NOALLOC_MAX_N
+    assert lib.adr_precompute_phi_noalloc(0, 4096, 1e-3, 4096, None, None, None) == adr.ADR_EINVAL
+    assert lib.adr_precompute_phi_noalloc(8, None, 1e-3, 4096, None, None, None) == adr.ADR_EINVAL
+    assert lib.adr_precompute_phi_noalloc(8, 4096, 0.0, 4096, None, None, None) == adr.ADR_EINVAL
+    assert lib.adr_precompute_phi_noalloc(8, 4096, 1e-3, None, None, None, None) == adr.ADR_EINVAL
+    assert lib.adr_precompute_phi_noalloc(nmax + 1, 4096, 1e-3, 4096, None, None, None) == adr.ADR_ENOMEM
     assert lib.adr_mode_product(3, n3, 3, 4096, 4096, 8192, 1.0, 0.0, None, None) == adr.ADR_EINVAL
     assert lib.adr_mode_product(3, n3, 0, 4096, 4096, 4096, 1.0, 0.0, None, None) == adr.ADR_EINVAL
     assert lib.adr_mode_product(4, n3, 0, 4096, 4096, 8192, 1.0, 0.0, None, None) == adr.ADR_EINVAL
