@@ -70,20 +70,62 @@ ModeArgs tucker_mode_args(const Geometry& g, const TuckerGroup& tg, int mu, cons
   return a;
 }
 
-// The tensor that direction mu of run_tucker's chain reads (mu > 0: a ping-pong buffer).
-const void* tucker_input(const TuckerGroup& tg, int k, int mu) {
+// The FP64 chain takes directions 1 and 2 in one pass over the (i1, i2) planes
+// where a plane fits in LDS (n1 = n2 = 64 or 128) and every tensor and matrix
+// of the group is 16-byte aligned.
+bool aligned16(const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; }
+bool tucker_plane12(const Geometry& g, const TuckerGroup& tg, int precision) {
+  if (precision != ADR_F64 || g.d < 2 || !mode12_plane_fits(g.n[0], g.n[1])) return false;
+  for (int k = 0; k < tg.count; ++k) {
+    if (!aligned16(tg.in[k]) || !aligned16(tg.out[k]) || !aligned16(tg.M[k][0]) ||
+        !aligned16(tg.M[k][1]) || (tg.Y[k] && !aligned16(tg.Y[k])))
+      return false;
+    if (g.d == 3 && !aligned16(tg.t1[k])) return false;
+  }
+  return true;
+}
+
+// The tensor that direction mu of run_tucker's chain reads (mu > 0: a ping-pong
+// buffer; after the two-direction plane pass, direction 3 reads t1).
+const void* tucker_input(const TuckerGroup& tg, int k, int mu, bool plane12 = false) {
+  if (plane12 && mu == 2) return tg.t1[k];
   return (mu == 0) ? tg.in[k] : ((mu % 2 == 1) ? tg.t1[k] : tg.t2[k]);
 }
 
 hipError_t run_tucker(const Geometry& g, const TuckerGroup& tg, double alpha, double beta,
                       int precision, hipStream_t s, bool last_f32 = false,
                       const Stage2Fuse* fuse = nullptr) {
-  for (int mu = 0; mu < g.d; ++mu) {
+  const bool plane12 = tucker_plane12(g, tg, precision);
+  if (plane12) {
+    // directions 1 and 2 in one pass: the whole operator when d = 2, else into t1
+    const double* W[kMaxGroup];
+    const double* M1[kMaxGroup];
+    const double* M2[kMaxGroup];
+    double* out[kMaxGroup];
+    const double* Y[kMaxGroup];
+    const bool whole = g.d == 2;
+    if (whole && fuse) return hipErrorInvalidValue;
+    for (int k = 0; k < tg.count; ++k) {
+      W[k] = static_cast<const double*>(tg.in[k]);
+      M1[k] = tg.M[k][0];
+      M2[k] = tg.M[k][1];
+      out[k] = static_cast<double*>(whole ? tg.out[k] : tg.t1[k]);
+      Y[k] = whole ? tg.Y[k] : nullptr;
+      if (!W[k] || !out[k] || (const void*)W[k] == (const void*)out[k]) return hipErrorInvalidValue;
+    }
+    const int planes = g.d == 3 ? g.n[2] : 1;
+    hipError_t e = timed(kKindMode, s, [&] {
+      return launch_mode12_plane(tg.count, W, M1, M2, out, Y, whole ? alpha : 1.0,
+                                 whole ? beta : 0.0, g.n[0], planes, s);
+    });
+    if (e != hipSuccess || whole) return e;
+  }
+  for (int mu = plane12 ? 2 : 0; mu < g.d; ++mu) {
     const bool last = (mu == g.d - 1);
     const void* W[kMaxGroup];
     void* out[kMaxGroup];
     for (int k = 0; k < tg.count; ++k) {
-      W[k] = tucker_input(tg, k, mu);
+      W[k] = tucker_input(tg, k, mu, plane12);
       out[k] = last ? tg.out[k] : ((mu % 2 == 0) ? tg.t1[k] : tg.t2[k]);
       if (!W[k] || !out[k] || W[k] == out[k]) return hipErrorInvalidValue;
     }
@@ -330,11 +372,12 @@ hipError_t step_etd2rkds(const adr_problem* p, const Geometry& g, const Carve& c
   const int last = g.d - 1;
   Stage2Fuse fuse{};
   bool fused = false;
-  if (g.d >= 2) {
+  const bool plane12 = tucker_plane12(g, tg, p->precision);
+  if (g.d >= 2 && !(plane12 && g.d == 2)) {
     const void* W[kMaxGroup];
     void* out[kMaxGroup];
     for (int cc = 0; cc < 2; ++cc) {
-      W[cc] = tucker_input(tg, cc, last);
+      W[cc] = tucker_input(tg, cc, last, plane12);
       out[cc] = tg.out[cc];
       fuse.R[cc] = (W[cc] == c.R[cc]) ? c.T[cc] : c.R[cc];
     }

@@ -73,6 +73,16 @@ hipError_t launch_mode_grouped_f64(TileCfg cfg, bool kfast, const TileJob* jobs,
 // Launchers (return hipSuccess or the launch error).
 hipError_t launch_mode_product_f64(const ModeArgs& a, hipStream_t s);
 
+// The products along directions 1 and 2 in one pass over the (i1, i2) planes
+// (FP64): out[:, :, p] = alpha * M1 W[:, :, p] M2^T (+ beta * Y[:, :, p]) for
+// p < planes, every tensor n x n x planes; n = n1 = n2 must be 64 or 128
+// (mode12_plane_fits) and every pointer 16-byte aligned.
+bool mode12_plane_fits(int n1, int n2);
+hipError_t launch_mode12_plane(int group, const double* const* W, const double* const* M1,
+                               const double* const* M2, double* const* out,
+                               const double* const* Y, double alpha, double beta, int n,
+                               int planes, hipStream_t s);
+
 // Reduced-precision "transposing" product (precision kLowpF32, kLowpBF16X3 or
 // kLowpBF16X2, the adr_precision values):
 //   out[x + X*i] = alpha * sum_k M[i,k] W[k + n*x] (+ beta * Y[x + X*i])

@@ -60,7 +60,10 @@ def test_mode_product_in_place_addend(dev):
     assert O.rel_inf_error(dev.from_device(out, shape), ref) <= TOL
 
 
-@pytest.mark.parametrize("shape", [(64, 64), (100, 37), (24, 36, 20), (130, 66, 72), (256, 256, 8)],
+@pytest.mark.parametrize("shape", [(64, 64), (100, 37), (24, 36, 20), (130, 66, 72), (256, 256, 8),
+                                   # (i1, i2) planes of 64^2 or 128^2 doubles: directions 1 and 2
+                                   # in one pass over LDS-resident planes (the whole operator in 2D)
+                                   (128, 128), (64, 64, 3), (128, 128, 1), (128, 128, 37), (64, 64, 200)],
                          ids=lambda s: "x".join(map(str, s)))
 def test_tucker_against_oracle(dev, shape):
     import torch
@@ -73,6 +76,21 @@ def test_tucker_against_oracle(dev, shape):
                    alpha=0.5, beta=2.0, Y=dev.to_device_f64(Y), work=work)
     torch.cuda.synchronize()
     ref = 0.5 * O.tucker(W, Ms) + 2.0 * Y
+    assert O.rel_inf_error(dev.from_device(out, shape), ref) <= TOL
+
+
+def test_tucker_plane_pass_in_place_addend(dev):
+    # the plane pass with out aliasing the addend Y (2D: the whole operator)
+    import torch
+    shape = (128, 128)
+    W, Y = _rand(shape, 11), _rand(shape, 12)
+    Ms = [_rand((128, 128), 40 + k) / math.sqrt(128) for k in range(2)]
+    out = dev.to_device_f64(Y)
+    work = torch.empty(dev.adr_tucker_workspace_bytes(shape) // 8 + 1, dtype=torch.float64, device="cuda")
+    dev.adr_tucker(shape, [dev.to_device_f64(M) for M in Ms], dev.to_device_f64(W), out,
+                   alpha=-1.25, beta=0.5, Y=out, work=work)
+    torch.cuda.synchronize()
+    ref = -1.25 * O.tucker(W, Ms) + 0.5 * Y
     assert O.rel_inf_error(dev.from_device(out, shape), ref) <= TOL
 
 

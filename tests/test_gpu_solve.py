@@ -79,6 +79,10 @@ CASES = [
     ("fhn3d_192x128x64_5", S.with_shape(S.fhn_3d(), (192, 128, 64)), 5),
     # strided direction with L % 128 != 0, L % 64 == 0: 64x64 tiles
     ("bruss3d_64x192x48_5", S.with_shape(S.brusselator_3d(), (64, 192, 48)), 5),
+    # 128^2 and 64^2 (i1, i2) planes: directions 1 and 2 in one pass over LDS
+    ("fhn3d_128x128x40_10", S.with_shape(S.fhn_3d(), (128, 128, 40)), 10),
+    ("bruss3d_64x64x96_10", S.with_shape(S.brusselator_3d(), (64, 64, 96)), 10),
+    ("schnakenberg2d_128x128_20", S.with_shape(S.schnakenberg_2d(), (128, 128)), 20),
 ]
 
 
