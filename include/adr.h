@@ -119,6 +119,23 @@ int adr_precompute_phi(int n, const double* A_dev, double tau, double* E_dev,
                        double* P1_dev, double* P2_dev, void* stream);
 
 /*
+ * adr_precompute_phi_batch -- adr_precompute_phi for `count` (1..4096)
+ * matrices with two synchronisations in all: the 1-norms of every tau_i A_i
+ * are read back together, then each matrix's polynomial and squarings run in
+ * turn on `stream` (same kernels and results as one call per matrix), and the
+ * call waits for them before returning.
+ *   n, tau        host arrays of `count` sizes (1..4096) and nonzero finite steps
+ *   A_dev         host array of `count` device matrices (n_i x n_i, column-major)
+ *   E_dev, P1_dev, P2_dev  host arrays of `count` device outputs, or NULL arrays;
+ *                 an entry may be NULL (not computed), but not all three of one matrix
+ * Works in the same kept per-device scratch as adr_precompute_phi, of
+ * 14 n_max^2 + 1 + count doubles.  Errors as adr_precompute_phi.
+ */
+int adr_precompute_phi_batch(int count, const int32_t* n, const double* const* A_dev,
+                             const double* tau, double* const* E_dev, double* const* P1_dev,
+                             double* const* P2_dev, void* stream);
+
+/*
  * adr_precompute_phi_noalloc -- adr_precompute_phi for callers that cannot
  * allocate device memory (tight serving loops, harnesses that forbid
  * hipMalloc): the same kernels and the same results, worked out in a fixed

@@ -81,6 +81,9 @@ def _load():
         "adr_build_1d_ops": (c_int, [c_int, c_double, c_double, c_double, c_double, c_int, c_void, c_void]),
         "adr_precompute_phi": (c_int, [c_int, c_void, c_double, c_void, c_void, c_void, c_void]),
         "adr_precompute_phi_noalloc": (c_int, [c_int, c_void, c_double, c_void, c_void, c_void, c_void]),
+        "adr_precompute_phi_batch": (c_int, [c_int, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(c_void),
+                                             ctypes.POINTER(c_double), ctypes.POINTER(c_void),
+                                             ctypes.POINTER(c_void), ctypes.POINTER(c_void), c_void]),
         "adr_workspace_bytes": (c_size, [ctypes.POINTER(AdrProblem)]),
         "adr_step": (c_int, [ctypes.POINTER(AdrProblem), c_void, c_void, c_void, c_size, c_void]),
         "adr_solve": (c_int, [ctypes.POINTER(AdrProblem), c_void, c_void, c_int, c_void, c_size, c_void]),
@@ -114,7 +117,7 @@ def _load():
 
 _lib = _load()
 EXPORTED = ("adr_strerror", "adr_version", "adr_build_1d_ops", "adr_precompute_phi",
-            "adr_precompute_phi_noalloc",
+            "adr_precompute_phi_noalloc", "adr_precompute_phi_batch",
             "adr_workspace_bytes", "adr_step", "adr_solve", "adr_mode_product",
             "adr_tucker_workspace_bytes", "adr_tucker", "adr_device_copy",
             "adr_timing_enable", "adr_timing_read", "adr_indicators_workspace_bytes",
@@ -205,6 +208,28 @@ def adr_precompute_phi_noalloc(A_dev: torch.Tensor, tau: float, E=None, P1=None,
                                            _ptr(outs[1]), _ptr(outs[2]), _stream(stream)),
            "adr_precompute_phi_noalloc")
     return tuple(outs)
+
+
+def adr_precompute_phi_batch(As, taus, stream=None):
+    """E, phi_1, phi_2 of tau_i * A_i for several device matrices (each an (n_i * n_i,)
+    float64 CUDA tensor, column-major) in one call with two synchronisations.
+    Returns a list of (E, P1, P2) tensors."""
+    count = len(As)
+    if len(taus) != count or count == 0:
+        raise ValueError("As and taus must be non-empty and of the same length")
+    ns, outs = [], []
+    for A in As:
+        _f64_cuda(A, "A_dev")
+        n = int(round(math.sqrt(A.numel())))
+        ns.append(n)
+        outs.append(tuple(torch.empty(n * n, dtype=torch.float64, device=A.device) for _ in range(3)))
+    n_arr = (ctypes.c_int32 * count)(*ns)
+    a_arr = (ctypes.c_void_p * count)(*[_ptr(A) for A in As])
+    t_arr = (ctypes.c_double * count)(*[float(t) for t in taus])
+    e_arr, p1_arr, p2_arr = ((ctypes.c_void_p * count)(*[_ptr(o[j]) for o in outs]) for j in range(3))
+    _check(_lib.adr_precompute_phi_batch(count, n_arr, a_arr, t_arr, e_arr, p1_arr, p2_arr,
+                                         _stream(stream)), "adr_precompute_phi_batch")
+    return outs
 
 
 def adr_workspace_bytes(problem: AdrProblem) -> int:
@@ -378,6 +403,7 @@ class Solver:
         self.stream = stream
         self.A_host = [[None] * self.d for _ in range(2)]
         self.keep = []  # device buffers referenced by the problem record
+        self.phi_matrices = 0   # distinct matrices whose functions were computed here
         p = AdrProblem()
         p.d = self.d
         for mu in range(3):
@@ -389,21 +415,37 @@ class Solver:
         for i, v in enumerate(w.params):
             p.params[i] = float(v)
         p.tau = float(w.tau)
+        # the 1D operators; directions (and components) with the same size, domain,
+        # diffusion and velocity share one device copy and one set of matrix functions
+        distinct = {}
+        slot = {}
         for c in range(2):
             vel = w.vel_u if c == 0 else w.vel_v
             for mu in range(self.d):
                 a, b = w.domain[mu]
-                A, band = adr_build_1d_ops(self.shape[mu], a, b, w.diff[c], vel[mu])
+                key = (self.shape[mu], float(a), float(b), float(w.diff[c]), float(vel[mu]))
+                if key not in distinct:
+                    A, band = adr_build_1d_ops(self.shape[mu], a, b, w.diff[c], vel[mu])
+                    A_dev = to_device_f64(A, device)
+                    band_dev = torch.from_numpy(np.ascontiguousarray(band.ravel())).to(device)
+                    self.keep += [A_dev, band_dev]
+                    distinct[key] = (A, A_dev, band_dev)
+                slot[(c, mu)] = key
+                A, A_dev, band_dev = distinct[key]
                 self.A_host[c][mu] = A
-                A_dev = to_device_f64(A, device)
-                self.keep.append(A_dev)
                 p.dense[c][mu] = A_dev.data_ptr()
                 if use_band:
-                    band_dev = torch.from_numpy(np.ascontiguousarray(band.ravel())).to(device)
-                    self.keep.append(band_dev)
                     p.band[c][mu] = band_dev.data_ptr()
+        if phis is None:
+            keys = list(distinct)
+            funcs = adr_precompute_phi_batch([distinct[k][1] for k in keys], [w.tau] * len(keys),
+                                             stream=stream)
+            by_key = dict(zip(keys, funcs))
+            self.phi_matrices = len(keys)
+        for c in range(2):
+            for mu in range(self.d):
                 if phis is None:
-                    E, P1, P2 = adr_precompute_phi(A_dev, w.tau, stream=stream)
+                    E, P1, P2 = by_key[slot[(c, mu)]]
                 else:
                     E, P1, P2 = (to_device_f64(phis[c][j][mu], device) for j in range(3))
                 self.keep += [E, P1, P2]

@@ -3,6 +3,7 @@
 // precompute, and kernel timing.  Implements include/adr.h.
 #include "adr.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -495,39 +496,29 @@ hipError_t gemm(int n, const double* A, const double* B, double* C, double alpha
 namespace adr {
 namespace host {
 
-// The body of adr_precompute_phi on a caller-chosen scratch: degree-18 Taylor
-// polynomials of the scaled matrix, then the modified squarings.
-int precompute_phi_in(int n, const double* A_dev, double tau, double* const outs[3],
-                      double* base, hipStream_t s) {
+// The scaling power of the Taylor step: the smallest s >= 0 with
+// ||tau A / 2^s||_1 <= 1.
+int phi_scaling_power(double norm) {
+  return norm > 1.0 ? (int)std::ceil(std::log2(norm)) : 0;
+}
+
+// Degree-18 Taylor polynomials of tau A / 2^sq, then sq modified squarings, in
+// `base` (phi_scratch_doubles(n) doubles), results copied to outs[j].  Enqueued
+// on `s` without any synchronisation.
+int precompute_phi_given(int n, const double* A_dev, double tau, int sq, double* const outs[3],
+                         double* base, hipStream_t s) {
   const size_t nn = (size_t)n * n;
-  // buffers: Y^1..Y^6, block B, Horner H, current E/P1/P2, next E/P1/P2, norm
-  constexpr int kBuf = 14;
   double* Yp[7];
   for (int j = 1; j <= 6; ++j) Yp[j] = base + nn * (j - 1);
   double* Bb = base + nn * 6;
   double* H = base + nn * 7;
   double* cur[3] = {base + nn * 8, base + nn * 9, base + nn * 10};
   double* nxt[3] = {base + nn * 11, base + nn * 12, base + nn * 13};
-  double* dnorm = base + nn * kBuf;
-  int status = ADR_OK;
-  auto fail = [&](int st) {
-    (void)hipStreamSynchronize(s);
-    return st;
-  };
-  // ||tau A||_1 sets the scaling power s with ||tau A / 2^s||_1 <= 1
-  if (launch_norm1(n, A_dev, tau, dnorm, s) != hipSuccess) return fail(ADR_EDEVICE);
-  double norm = 0.0;
-  if (hipMemcpyAsync(&norm, dnorm, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
-    return fail(ADR_EDEVICE);
-  if (hipStreamSynchronize(s) != hipSuccess) return fail(ADR_EDEVICE);
-  if (!std::isfinite(norm)) return fail(ADR_ENONFINITE);
-  int sq = 0;
-  if (norm > 1.0) sq = (int)std::ceil(std::log2(norm));
   const double scale = std::ldexp(tau, -sq);
   hipError_t e = launch_scale_copy((long long)nn, A_dev, scale, Yp[1], s);
   for (int j = 2; j <= 6 && e == hipSuccess; ++j)
     e = gemm(n, Yp[j - 1], Yp[1], Yp[j], 1.0, 0.0, nullptr, 0.0, nullptr, s);
-  if (e != hipSuccess) return fail(ADR_EDEVICE);
+  if (e != hipSuccess) return ADR_EDEVICE;
   // Taylor polynomials of degree 18 of exp, phi_1, phi_2 (coefficients 1/(k+l)!) in
   // Paterson-Stockmeyer form: p = B0 + (B1 + (B2 + c18 Y^6) Y^6) Y^6, Bj = sum_i c_{6j+i} Y^i
   for (int l = 0; l < 3 && e == hipSuccess; ++l) {
@@ -560,7 +551,7 @@ int precompute_phi_in(int n, const double* A_dev, double tau, double* const outs
     if (e == hipSuccess) e = block(0, Bb, false);                                    // B0
     if (e == hipSuccess) e = gemm(n, nxt[l], Yp[6], cur[l], 1.0, 1.0, Bb, 0.0, nullptr, s);
   }
-  if (e != hipSuccess) return fail(ADR_EDEVICE);
+  if (e != hipSuccess) return ADR_EDEVICE;
   // modified squaring: e^{2X} = (e^X)^2, phi_1(2X) = (e^X phi_1 + phi_1)/2,
   // phi_2(2X) = (e^X phi_2 + phi_1 + phi_2)/4
   for (int it = 0; it < sq && e == hipSuccess; ++it) {
@@ -571,9 +562,29 @@ int precompute_phi_in(int n, const double* A_dev, double tau, double* const outs
   }
   for (int j = 0; j < 3 && e == hipSuccess; ++j)
     if (outs[j]) e = launch_copy_f64(cur[j], outs[j], nn, s);
-  if (e != hipSuccess) return fail(ADR_EDEVICE);
-  if (hipStreamSynchronize(s) != hipSuccess) status = ADR_EDEVICE;
-  return status;
+  if (e != hipSuccess) return ADR_EDEVICE;
+  return ADR_OK;
+}
+
+// The body of adr_precompute_phi on a caller-chosen scratch: ||tau A||_1 read
+// back (one synchronisation), then precompute_phi_given, then a final
+// synchronisation.
+int precompute_phi_in(int n, const double* A_dev, double tau, double* const outs[3],
+                      double* base, hipStream_t s) {
+  double* dnorm = base + (size_t)n * n * 14;
+  auto fail = [&](int st) {
+    (void)hipStreamSynchronize(s);
+    return st;
+  };
+  if (launch_norm1(n, A_dev, tau, dnorm, s) != hipSuccess) return fail(ADR_EDEVICE);
+  double norm = 0.0;
+  if (hipMemcpyAsync(&norm, dnorm, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return fail(ADR_EDEVICE);
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(ADR_EDEVICE);
+  if (!std::isfinite(norm)) return fail(ADR_ENONFINITE);
+  const int st = precompute_phi_given(n, A_dev, tau, phi_scaling_power(norm), outs, base, s);
+  if (st != ADR_OK) return fail(st);
+  return hipStreamSynchronize(s) == hipSuccess ? ADR_OK : ADR_EDEVICE;
 }
 
 }  // namespace host
@@ -670,6 +681,60 @@ int adr_precompute_phi(int n, const double* A_dev, double tau, double* E_dev, do
   }
   double* outs[3] = {E_dev, P1_dev, P2_dev};
   return precompute_phi_in(n, A_dev, tau, outs, static_cast<double*>(sc.ptr), s);
+}
+
+int adr_precompute_phi_batch(int count, const int32_t* n, const double* const* A_dev,
+                             const double* tau, double* const* E_dev, double* const* P1_dev,
+                             double* const* P2_dev, void* stream) {
+  if (count < 1 || count > 4096 || !n || !A_dev || !tau) return ADR_EINVAL;
+  int nmax = 0;
+  for (int i = 0; i < count; ++i) {
+    if (n[i] < 1 || n[i] > 4096 || !A_dev[i] || !std::isfinite(tau[i]) || tau[i] == 0.0)
+      return ADR_EINVAL;
+    if (!(E_dev && E_dev[i]) && !(P1_dev && P1_dev[i]) && !(P2_dev && P2_dev[i])) return ADR_EINVAL;
+    nmax = std::max(nmax, (int)n[i]);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lock(g_phi_mu);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ADR_EDEVICE;
+  PhiScratch& sc = g_phi_scratch[dev];
+  // one work area for the matrices in turn (stream order), and the norms after it
+  const size_t work = phi_scratch_doubles(nmax);
+  const size_t need = sizeof(double) * (work + count);
+  if (sc.cap < need) {
+    if (sc.ptr) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(sc.ptr);
+      sc.ptr = nullptr;
+      sc.cap = 0;
+    }
+    if (hipMalloc(&sc.ptr, need) != hipSuccess) return ADR_ENOMEM;
+    sc.cap = need;
+  }
+  double* base = static_cast<double*>(sc.ptr);
+  double* dnorms = base + work;
+  auto fail = [&](int st) {
+    (void)hipStreamSynchronize(s);
+    return st;
+  };
+  for (int i = 0; i < count; ++i)
+    if (launch_norm1(n[i], A_dev[i], tau[i], dnorms + i, s) != hipSuccess) return fail(ADR_EDEVICE);
+  std::vector<double> norms(count);
+  if (hipMemcpyAsync(norms.data(), dnorms, sizeof(double) * count, hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(ADR_EDEVICE);
+  for (int i = 0; i < count; ++i)
+    if (!std::isfinite(norms[i])) return fail(ADR_ENONFINITE);
+  for (int i = 0; i < count; ++i) {
+    double* outs[3] = {E_dev ? E_dev[i] : nullptr, P1_dev ? P1_dev[i] : nullptr,
+                       P2_dev ? P2_dev[i] : nullptr};
+    const int st = precompute_phi_given(n[i], A_dev[i], tau[i], phi_scaling_power(norms[i]), outs,
+                                        base, s);
+    if (st != ADR_OK) return fail(st);
+  }
+  return hipStreamSynchronize(s) == hipSuccess ? ADR_OK : ADR_EDEVICE;
 }
 
 size_t adr_workspace_bytes(const adr_problem* p) {

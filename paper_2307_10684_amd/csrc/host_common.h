@@ -87,6 +87,11 @@ Carve carve(const adr_problem* p, const Geometry& g, char* base);
 constexpr size_t phi_scratch_doubles(int n) { return (size_t)n * n * 14 + 1; }
 int precompute_phi_in(int n, const double* A_dev, double tau, double* const outs[3],
                       double* base, hipStream_t s);
+// Its parts: the scaling power for ||tau A||_1, and the polynomial and squarings
+// for a given power (enqueued without synchronisation).
+int phi_scaling_power(double norm);
+int precompute_phi_given(int n, const double* A_dev, double tau, int sq, double* const outs[3],
+                         double* base, hipStream_t s);
 int check_problem(const adr_problem* p, Geometry& g);
 Reaction reaction_of(const adr_problem* p);
 hipError_t prepare_lowp(const adr_problem* p, const Geometry& g, const Carve& c, hipStream_t s);

@@ -33,6 +33,11 @@ Backend protocol::
     release(handle)                free the request's device memory
     release_plan(plan)             free a plan (no run of it is pending)
     solve_alone(handle, steps) -> token   (sequential reference path)
+
+Optional: ``held() -> int`` device bytes the backend holds outside any request
+(work areas kept until the process ends), and ``held_extra(job) -> int`` the
+bytes admitting ``job`` would add to that for good (a kept work area that has
+to grow).  The engine counts both against the budget.
 """
 from __future__ import annotations
 
@@ -213,16 +218,19 @@ class Engine:
                                        "cancelled"))
             for sl in [x for x in slots if is_cancelled(x.job) and not in_flight(x)]:
                 finish(sl, now(), None, "cancelled")
-            # admission: first come, first served, while slots and budget allow
+            # admission: first come, first served, while slots and budget allow; memory
+            # the backend keeps for good (and its growth for this request) counts too
             while queue and len(slots) < self.max_active:
                 job = queue[0]
                 need = int(be.footprint(job))
-                if need > self.budget:
+                held = int(be.held()) if hasattr(be, "held") else 0
+                extra = int(be.held_extra(job)) if hasattr(be, "held_extra") else 0
+                if held + extra + need > self.budget:
                     queue.popleft()
                     done.append(Completion(job.rid, job.arrival, now(), now(), job.steps, job.N,
                                            "rejected"))
                     continue
-                if used + need > self.budget:
+                if held + extra + used + need > self.budget:
                     break
                 queue.popleft()
                 try:
@@ -236,7 +244,8 @@ class Engine:
                 s = _Slot(serial, job, handle, need, now(), job.steps)
                 slots.append(s)
                 lane_of_slot[s.serial] = self.lane_of(job)
-                peak_used = max(peak_used, used)
+                held_now = int(be.held()) if hasattr(be, "held") else 0
+                peak_used = max(peak_used, used + held_now)
                 peak_active = max(peak_active, len(slots))
                 if job.steps == 0:
                     res = None
@@ -315,6 +324,7 @@ class Engine:
             "p99_latency_s": float(np.percentile(lat, 99)),
             "mean_wait_s": float(np.mean([c.wait for c in ok])) if ok else 0.0,
             "peak_bytes": peak_used, "peak_active": peak_active,
+            "held_bytes": int(be.held()) if hasattr(be, "held") else 0,
             "rounds": rounds, "plans_built": nplans, "lanes": len(lanes),
         }
         return sorted(done, key=lambda c: c.rid)
@@ -361,7 +371,8 @@ class _Handle:
 
 class GpuBackend:
     """Backend on the HIP library: per-request operators and matrix functions
-    built on a set-up stream (adr_build_1d_ops, adr_precompute_phi), grouped
+    built on a set-up stream (adr_build_1d_ops; adr_precompute_phi_batch for
+    the request's distinct matrices, two synchronisations), grouped
     plans (adr_batch_*) run on one compute stream per lane, results copied back
     on a copy stream into pinned host memory.  All streams have the default
     priority."""
@@ -377,6 +388,25 @@ class GpuBackend:
         self.lanes = {}             # lane -> compute stream (created on first use)
         self.setup = torch.cuda.Stream(device)
         self.copy = torch.cuda.Stream(device)
+        # the matrix functions are computed in a work area the library keeps per
+        # device and grows to the largest side it has seen (14 n^2 + 1 + count
+        # doubles; see adr_precompute_phi_batch)
+        self._phi_side = 0
+
+    # the library's fixed work area of adr_precompute_phi_noalloc (held once the
+    # library is loaded) plus the kept work area of the matrix-function precompute
+    _NOALLOC_BYTES = 8 * (14 * 512 * 512 + 1)
+
+    @staticmethod
+    def _phi_area(side: int) -> int:
+        return 8 * (14 * side * side + 1 + 6) if side > 0 else 0
+
+    def held(self) -> int:
+        return self._NOALLOC_BYTES + self._phi_area(self._phi_side)
+
+    def held_extra(self, job: Job) -> int:
+        side = max(int(x) for x in job.workload.n)
+        return max(0, self._phi_area(side) - self._phi_area(self._phi_side))
 
     def _lane(self, lane: int):
         if lane not in self.lanes:
@@ -406,6 +436,7 @@ class GpuBackend:
             p = adr_batch_create([s.problem], [h.U], [h.V], [s.work], 0, self.setup)
             adr_batch_destroy(p)
         self.setup.synchronize()
+        self._phi_side = max(self._phi_side, max(int(x) for x in job.workload.n))
         h.solver = s
         h.shape = s.shape
         h.hostU = h.hostV = None
@@ -413,6 +444,10 @@ class GpuBackend:
 
     def plan(self, handles):
         from . import ADR_BATCH_GRAPH, ADR_BATCH_PREPARED, adr_batch_create
+        if len(handles) == 1:
+            # a lane with one request steps it with the single-problem path, whose
+            # tile shapes are chosen for that problem alone
+            return ("single", handles[0])
         flags = ADR_BATCH_PREPARED if self.precision == "f32" else 0
         if self.graph:
             flags |= ADR_BATCH_GRAPH
@@ -421,9 +456,13 @@ class GpuBackend:
                                 self.setup)
 
     def launch(self, plan, steps: int, lane: int = 0):
-        from . import adr_batch_run
+        from . import adr_batch_run, adr_solve
         st = self._lane(lane)
-        adr_batch_run(plan, steps, st)
+        if isinstance(plan, tuple):
+            h = plan[1]
+            adr_solve(h.solver.problem, h.U, h.V, steps, h.solver.work, st)
+        else:
+            adr_batch_run(plan, steps, st)
         ev = self.torch.cuda.Event()
         ev.record(st)
         return ev
@@ -468,4 +507,5 @@ class GpuBackend:
 
     def release_plan(self, plan):
         from . import adr_batch_destroy
-        adr_batch_destroy(plan)
+        if not isinstance(plan, tuple):
+            adr_batch_destroy(plan)

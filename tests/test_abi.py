@@ -130,6 +130,21 @@ def test_other_entry_points_validate(adr):
     assert lib.adr_precompute_phi(8, None, 1e-3, 4096, None, None, None) == adr.ADR_EINVAL
     assert lib.adr_precompute_phi(8, 4096, float("nan"), 4096, None, None, None) == adr.ADR_EINVAL
     assert lib.adr_precompute_phi(8, 4096, 1e-3, None, None, None, None) == adr.ADR_EINVAL
+    # the batched variant: count, sizes, steps and outputs are checked before device work
+    n2 = (ctypes.c_int32 * 2)(8, 8)
+    a2 = (ctypes.c_void_p * 2)(4096, 4096)
+    t2 = (ctypes.c_double * 2)(1e-3, 1e-3)
+    o2 = (ctypes.c_void_p * 2)(4096, 4096)
+    nul2 = (ctypes.c_void_p * 2)(4096, None)
+    assert lib.adr_precompute_phi_batch(0, n2, a2, t2, o2, None, None, None) == adr.ADR_EINVAL
+    assert lib.adr_precompute_phi_batch(4097, n2, a2, t2, o2, None, None, None) == adr.ADR_EINVAL
+    assert lib.adr_precompute_phi_batch(2, None, a2, t2, o2, None, None, None) == adr.ADR_EINVAL
+    bad_n = (ctypes.c_int32 * 2)(8, 0)
+    assert lib.adr_precompute_phi_batch(2, bad_n, a2, t2, o2, None, None, None) == adr.ADR_EINVAL
+    bad_t = (ctypes.c_double * 2)(1e-3, float("inf"))
+    assert lib.adr_precompute_phi_batch(2, n2, a2, bad_t, o2, None, None, None) == adr.ADR_EINVAL
+    # the second matrix asks for no output at all
+    assert lib.adr_precompute_phi_batch(2, n2, a2, t2, nul2, None, None, None) == adr.ADR_EINVAL
     # the no-allocation variant: same checks, and sizes beyond its fixed work area
     nmax = adr.ADR_PHI_NOALLOC_MAX_N
     assert lib.adr_precompute_phi_noalloc(0, 4096, 1e-3, 4096, None, None, None) == adr.ADR_EINVAL

@@ -154,3 +154,29 @@ def test_device_copy(dev):
     dev.adr_device_copy(x, y, x.numel())
     torch.cuda.synchronize()
     assert torch.equal(x, y)
+
+
+def test_precompute_phi_batch_equals_single_calls(dev):
+    # several matrices of different sizes and steps in one call (two
+    # synchronisations): the same kernels as one call per matrix, so bitwise equal
+    import torch
+    specs = [(256, 5e-3, 1e-3, 0.1), (64, 1e-3, 10.0, 0.0), (300, 2e-3, 0.5, -0.2),
+             (3, 0.1, 1.0, 0.0), (512, 1e-3, 10.0, 0.0)]
+    As = [dev.to_device_f64(O.operator_1d(n, 0.0, 1.0, d, v)) for n, _, d, v in specs]
+    taus = [t for _, t, _, _ in specs]
+    batch = dev.adr_precompute_phi_batch(As, taus)
+    torch.cuda.synchronize()
+    for A, tau, got in zip(As, taus, batch):
+        ref = dev.adr_precompute_phi(A, tau)
+        torch.cuda.synchronize()
+        for g, r in zip(got, ref):
+            assert torch.equal(g, r)
+
+
+def test_precompute_phi_batch_rejects_nonfinite(dev):
+    good = dev.to_device_f64(np.eye(8))
+    bad = np.eye(8)
+    bad[1, 2] = np.nan
+    with pytest.raises(dev.AdrError) as ei:
+        dev.adr_precompute_phi_batch([good, dev.to_device_f64(bad)], [1e-3, 1e-3])
+    assert ei.value.status == dev.ADR_ENONFINITE

@@ -334,3 +334,54 @@ def test_cancellation_of_running_and_queued_requests():
         assert done[j.rid].status == "ok"
         assert np.array_equal(done[j.rid].result[0], U) and np.array_equal(done[j.rid].result[1], V)
     assert be.live == 0 and be.mem == 0 and be.plans_alive == 0
+
+
+class HeldBackend(FakeBackend):
+    """A backend that keeps a work area growing with the largest grid side it
+    has set up (like the library's matrix-function scratch) and a fixed one."""
+
+    def __init__(self, clock, base=10_000, per_side2=100, **kw):
+        super().__init__(clock, **kw)
+        self.base, self.per_side2, self.side = base, per_side2, 0
+
+    def _area(self, side):
+        return self.per_side2 * side * side
+
+    def held(self):
+        return self.base + self._area(self.side)
+
+    def held_extra(self, job):
+        side = max(job.workload.n)
+        return max(0, self._area(side) - self._area(self.side))
+
+    def admit(self, job):
+        h = super().admit(job)
+        self.side = max(self.side, max(job.workload.n))
+        return h
+
+
+def test_held_memory_counts_against_the_budget():
+    # the kept work area is part of every admission check: with it the device
+    # never goes over the budget, and a request whose growth of the area cannot
+    # fit even on an empty device is rejected
+    clock = Clock()
+    be = HeldBackend(clock, cost=1e-7)
+    small_w = S.with_shape(S.schnakenberg_2d(), (16, 16))
+    small = [serving.Job(k, 0.0, small_w, 3, lambda: S.initial_state(small_w, 0))
+             for k in range(4)]
+    big_w = S.with_shape(S.schnakenberg_2d(), (40, 40))
+    big = serving.Job(9, 0.0, big_w, 2, lambda: S.initial_state(big_w, 0))
+    fp_small = be.footprint(small[0])
+    # three small requests fit the budget, but not beside the held memory
+    budget = be.base + be._area(16) + 3 * fp_small - 1
+    assert 3 * fp_small <= budget
+    eng = serving.Engine(be, budget_bytes=budget, max_active=8, max_chunk=2,
+                         clock=clock, sleep=clock.sleep)
+    done = eng.run(small + [big])
+    status = {c.rid: c.status for c in done}
+    assert status[9] == "rejected"                      # 100 * 40^2 alone exceeds the budget
+    assert all(status[k] == "ok" for k in range(4))
+    assert be.peak_mem + be.held() <= budget
+    assert eng.stats["peak_bytes"] <= budget and eng.stats["held_bytes"] == be.held()
+    # counting the held memory, two small requests run at once, not three
+    assert eng.stats["peak_active"] == 2
