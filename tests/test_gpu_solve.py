@@ -83,6 +83,9 @@ CASES = [
     ("fhn3d_128x128x40_10", S.with_shape(S.fhn_3d(), (128, 128, 40)), 10),
     ("bruss3d_64x64x96_10", S.with_shape(S.brusselator_3d(), (64, 64, 96)), 10),
     ("schnakenberg2d_128x128_20", S.with_shape(S.schnakenberg_2d(), (128, 128)), 20),
+    # 3D grids of 2^20 points or more with n1 = 64 or 256: stage 1 by whole-row waves
+    ("fhn3d_64x128x128_5", S.with_shape(S.fhn_3d(), (64, 128, 128)), 5),
+    ("bruss3d_256x64x72_3", S.with_shape(S.brusselator_3d(), (256, 64, 72)), 3),
 ]
 
 
