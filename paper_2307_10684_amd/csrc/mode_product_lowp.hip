@@ -66,6 +66,7 @@ struct LowpArgs {
 };
 
 constexpr int kThreads = 256;
+constexpr int kOutF32 = 0, kOutF64 = 1;   // output of the wide kernel
 
 // the product g of a single launch as a job
 __device__ __forceinline__ LowpJob job_of(const LowpArgs& a, int g) {
@@ -537,6 +538,113 @@ __global__ __launch_bounds__(64 * WI * WX, 2) void k_tgemm_bf16s(LowpArgs a, int
   tgemm_epilogue<FI, FX, TI, TX, OUT64>(job_of(a, g), acc, i0 + wi * TI, x0 + wx * TX, col, kq);
 }
 
+// The split product with the operands' roles exchanged: A is the W fragment
+// (its rows are fibres x), B the M fragment (its columns are rows i), so the
+// block holds out^T and a lane ends with four consecutive fibres of one row.
+// The parts are multiplied in split_mfma's order (pm, pw) = (2,0), (1,1), (0,2),
+// (1,0), (0,1), (0,0): each of the 16 x 16 sums adds the same products in the
+// same order as split_mfma(M, W) does.
+template <int PARTS>
+__device__ __forceinline__ f4 split_mfma_t(const s8 (&w)[PARTS], const s8 (&m)[PARTS], f4 acc) {
+  if constexpr (PARTS == 3) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[0], m[2], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[1], m[1], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[2], m[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[0], m[1], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[1], m[0], acc, 0, 0, 0);
+  } else {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[0], m[1], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[1], m[0], acc, 0, 0, 0);
+  }
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[0], m[0], acc, 0, 0, 0);
+}
+
+// Epilogue of a wave's 64 x 64 block in the exchanged layout: acc[fx][fi][v] is
+// out[x + X i] with x = xb + 16 fx + 4 krow + v, i = ib + 16 fi + col, so each
+// lane writes four consecutive elements of a row: 16 bytes of FP32 or 32 bytes
+// of FP64.  The FP64 form reads its addends the same way (Y may alias out:
+// every element is read and then written by one lane), the loads of the next
+// 16 x 16 block issued before the stores of this one.
+template <int OUTK, int PARTS, bool HASY, bool HASZ>
+__device__ __forceinline__ void wide_epilogue(const LowpArgs& a, int g, const f4 (&acc)[4][4],
+                                              int ib, unsigned xb, int col, int krow) {
+  constexpr int FX = 4, FI = 4;
+  const unsigned X = a.X;
+  const double alpha = a.alpha;
+  auto index = [&](int fx, int fi) {
+    return xb + (unsigned)(fx * 16 + 4 * krow) + X * (unsigned)(ib + fi * 16 + col);
+  };
+  if constexpr (OUTK == kOutF32) {
+    float* out = static_cast<float*>(a.out[g]);
+#pragma unroll
+    for (int fx = 0; fx < FX; ++fx)
+#pragma unroll
+      for (int fi = 0; fi < FI; ++fi) {
+        f4 o;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[v] = (float)(alpha * (double)acc[fx][fi][v]);
+        *reinterpret_cast<f4*>(out + index(fx, fi)) = o;
+      }
+  } else {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    double* out = static_cast<double*>(a.out[g]);
+    const double* Y = a.Y[g];
+    const float* Z = a.Z[g];
+    const double beta = a.beta;
+    d2 y[2][2];
+    f4 z[2];
+    // block b = (fx, fi) = (b / FI, b % FI)
+    auto load = [&](int b) {
+      const unsigned o = index(b / FI, b % FI);
+      if (HASY) {
+        y[b & 1][0] = *reinterpret_cast<const d2*>(Y + o);
+        y[b & 1][1] = *reinterpret_cast<const d2*>(Y + o + 2);
+      }
+      if (HASZ) z[b & 1] = *reinterpret_cast<const f4*>(Z + o);
+    };
+    load(0);
+#pragma unroll
+    for (int b = 0; b < FX * FI; ++b) {
+      if (b + 1 < FX * FI) load(b + 1);
+      const int fx = b / FI, fi = b % FI;
+      double val[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double p = alpha * (double)acc[fx][fi][v];
+        const double yv = HASY ? y[b & 1][v / 2][v % 2] : 0.0;
+        if (HASZ) val[v] = ((HASY ? beta * yv : 0.0) + (double)z[b & 1][v]) + p;
+        else if (HASY) val[v] = p + beta * yv;
+        else val[v] = p;
+      }
+      const unsigned o = index(fx, fi);
+      *reinterpret_cast<d2*>(out + o) = d2{val[0], val[1]};
+      *reinterpret_cast<d2*>(out + o + 2) = d2{val[2], val[3]};
+    }
+  }
+}
+
+// LDS-direct copy of SPANS x 16 rows of a 32-deep chunk of PARTS bf16 planes:
+// rows row0 + R0 + (0 .. 16 SPANS - 1) (row stride n, elements k0 .. k0 + 31)
+// into LDS rows R0 onward (64 bytes each, quad q of row r in slot
+// q ^ ((r >> 1) & 3)).  Lane l fills row R0 + 16 h + l / 4, slot l % 4, with the
+// quad that slot holds; one wave instruction fills one 1 KB span.
+template <int PARTS, int PLANE, int SPANS>
+__device__ __forceinline__ void dma_split_rows(unsigned short* dst,
+                                               const unsigned short* const* planes,
+                                               unsigned row0, int n, int k0, int R0) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int h = 0; h < SPANS; ++h) {
+    const int Rh = R0 + 16 * h;
+    const int r = Rh + (lane >> 2);
+    const int q = (lane & 3) ^ ((r >> 1) & 3);
+    const unsigned src = (row0 + (unsigned)r) * (unsigned)n + (unsigned)(k0 + 8 * q);
+#pragma unroll
+    for (int pp = 0; pp < PARTS; ++pp)
+      __builtin_amdgcn_global_load_lds(planes[pp] + src, dst + pp * PLANE + Rh * 32, 16, 0, 0);
+  }
+}
+
 // Wide tiles for evenly tiled shapes (n % 256 == 0, X % 128 == 0): 256 rows x
 // 128 fibres per workgroup, eight waves in a 4 x 2 grid of 64 x 64 wave
 // tiles, one workgroup per CU walking the tiles of the launch (persistent:
@@ -544,14 +652,15 @@ __global__ __launch_bounds__(64 * WI * WX, 2) void k_tgemm_bf16s(LowpArgs a, int
 // parts: 96 KB of M, 48 KB of W).  The M planes arrive pre-split and go from
 // global memory straight into LDS (global_load_lds, lane l writing bytes
 // 16 l onward of the wave's 1 KB span); W arrives as FP32, is split in
-// registers and stored.  Each LDS row holds 32 bf16 (four 16-byte quads), and
-// quad q of row r sits in slot q ^ ((r >> 1) & 3): the eight rows a fragment
-// read puts in one 128-byte bank window then use all eight 16-byte slots.
-// The next chunk (of this tile, or the first of the next) is in flight while
-// the current one is multiplied; the two buffers are distinct LDS objects and
-// the chunk loop is unrolled by two, so the loads into one buffer are waited
-// for only at the barrier.
-template <int PARTS, bool OUT64>
+// registers and stored.  Each LDS row
+// holds 32 bf16 (four 16-byte quads), and quad q of row r sits in slot
+// q ^ ((r >> 1) & 3): the eight rows a fragment read puts in one 128-byte bank
+// window then use all eight 16-byte slots.  The next chunk (of this tile, or
+// the first of the next) is in flight while the current one is multiplied;
+// the two buffers are distinct LDS objects and the chunk loop is unrolled by
+// two, so the loads into one buffer are waited for only at the barrier.  The
+// output is FP32 or FP64 with the addends (OUTK).
+template <int PARTS, int OUTK>
 __global__ __launch_bounds__(512, 1) void k_tgemm_bf16s_wide(LowpArgs a, int n_itiles,
                                                             int n_xtiles, int ntiles) {
   constexpr int BI = 256, BX = 128, BK = 32, WX = 2;
@@ -581,25 +690,15 @@ __global__ __launch_bounds__(512, 1) void k_tgemm_bf16s_wide(LowpArgs a, int n_i
     return T;
   };
 
-  // M chunk: per part 256 rows x 64 bytes = 16 spans of 1 KB (16 rows each); wave
-  // w fills rows 32 w .. 32 w + 31.  Lane l of a span fills row R0 + l / 4, slot
-  // l % 4, with the quad that the slot holds.
-  const int dma_r = lane >> 2, dma_slot = lane & 3;
+  // M chunk: per part 256 rows x 64 bytes = 16 spans of 1 KB (16 rows each);
+  // wave w fills rows 32 w .. 32 w + 31.
   auto dma_m = [&](unsigned short* dst, const Tile& T, int k0) {
+    const unsigned short* planes[PARTS];
 #pragma unroll
-    for (int pp = 0; pp < PARTS; ++pp) {
-      const unsigned short* __restrict__ Mp = a.Mp[T.g][pp];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int R0 = 32 * wave + 16 * h;
-        const int r = R0 + dma_r;
-        const int q = dma_slot ^ ((r >> 1) & 3);
-        const unsigned src = (unsigned)(T.i0 + r) * (unsigned)n + (unsigned)(k0 + 8 * q);
-        __builtin_amdgcn_global_load_lds(Mp + src, dst + pp * PLANE_M + R0 * BK, 16, 0, 0);
-      }
-    }
+    for (int pp = 0; pp < PARTS; ++pp) planes[pp] = a.Mp[T.g][pp];
+    dma_split_rows<PARTS, PLANE_M, 2>(dst, planes, (unsigned)T.i0, n, k0, 32 * wave);
   };
-  // W chunk: 128 fibres x 32 k FP32; thread t takes fibre t / 4, k-quad t % 4
+  // FP32 W chunk: 128 fibres x 32 k; thread t takes fibre t / 4, k-quad t % 4
   const int w_x = tid >> 2, w_q = tid & 3;
   const int w_slot = w_q ^ ((w_x >> 1) & 3);
   f4 rw0, rw1;
@@ -626,24 +725,41 @@ __global__ __launch_bounds__(512, 1) void k_tgemm_bf16s_wide(LowpArgs a, int n_i
   // fragment reads: row r (low four bits = lane % 16), quad lane / 16
   const int col = lane & 15, kq = lane >> 4;
   const int frag_off = 8 * (kq ^ ((col >> 1) & 3));
-  f4 acc[FI][FX];
+  f4 acc[FX][FI];
   auto compute = [&](const unsigned short* cm, const unsigned short* cw) {
-    s8 af[FI][PARTS];
+    s8 mf[FI][PARTS];
 #pragma unroll
     for (int fi = 0; fi < FI; ++fi)
 #pragma unroll
       for (int pp = 0; pp < PARTS; ++pp)
-        af[fi][pp] = *reinterpret_cast<const s8*>(cm + pp * PLANE_M +
+        mf[fi][pp] = *reinterpret_cast<const s8*>(cm + pp * PLANE_M +
                                                   (wi * TI + fi * 16 + col) * BK + frag_off);
 #pragma unroll
     for (int fx = 0; fx < FX; ++fx) {
-      s8 bf[PARTS];
+      s8 wf[PARTS];
 #pragma unroll
       for (int pp = 0; pp < PARTS; ++pp)
-        bf[pp] = *reinterpret_cast<const s8*>(cw + pp * PLANE_W +
+        wf[pp] = *reinterpret_cast<const s8*>(cw + pp * PLANE_W +
                                               (wx * TX + fx * 16 + col) * BK + frag_off);
 #pragma unroll
-      for (int fi = 0; fi < FI; ++fi) acc[fi][fx] = split_mfma<PARTS>(af[fi], bf, acc[fi][fx]);
+      for (int fi = 0; fi < FI; ++fi) acc[fx][fi] = split_mfma_t<PARTS>(wf, mf[fi], acc[fx][fi]);
+    }
+  };
+  auto epilogue = [&](const Tile& T) {
+    const int ib = T.i0 + wi * TI;
+    const unsigned xb = T.x0 + wx * TX;
+    if constexpr (OUTK == kOutF64) {
+      const bool hy = a.Y[T.g] != nullptr, hz = a.Z[T.g] != nullptr;
+      if (hz) {
+        if (hy) wide_epilogue<OUTK, PARTS, true, true>(a, T.g, acc, ib, xb, col, kq);
+        else wide_epilogue<OUTK, PARTS, false, true>(a, T.g, acc, ib, xb, col, kq);
+      } else if (hy) {
+        wide_epilogue<OUTK, PARTS, true, false>(a, T.g, acc, ib, xb, col, kq);
+      } else {
+        wide_epilogue<OUTK, PARTS, false, false>(a, T.g, acc, ib, xb, col, kq);
+      }
+    } else {
+      wide_epilogue<OUTK, PARTS, false, false>(a, T.g, acc, ib, xb, col, kq);
     }
   };
 
@@ -659,9 +775,9 @@ __global__ __launch_bounds__(512, 1) void k_tgemm_bf16s_wide(LowpArgs a, int n_i
     const bool next_tile = tn < ntiles;
     const Tile nxt = tile_of(next_tile ? tn : t);
 #pragma unroll
-    for (int fi = 0; fi < FI; ++fi)
+    for (int fx = 0; fx < FX; ++fx)
 #pragma unroll
-      for (int fx = 0; fx < FX; ++fx) acc[fi][fx] = f4{0.f, 0.f, 0.f, 0.f};
+      for (int fi = 0; fi < FI; ++fi) acc[fx][fi] = f4{0.f, 0.f, 0.f, 0.f};
     // chunk c from (cm, cw); the next chunk goes into (nm, nw)
     auto step = [&](int c, const unsigned short* cm, const unsigned short* cw, unsigned short* nm,
                     unsigned short* nw) {
@@ -681,8 +797,7 @@ __global__ __launch_bounds__(512, 1) void k_tgemm_bf16s_wide(LowpArgs a, int n_i
       step(c, sM0, sW0, sM1, sW1);
       step(c + 1, sM1, sW1, sM0, sW0);
     }
-    tgemm_epilogue<FI, FX, TI, TX, OUT64, 1>(job_of(a, cur.g), acc, cur.i0 + wi * TI,
-                                             cur.x0 + wx * TX, col, kq);
+    epilogue(cur);
     if (!next_tile) break;
     t = tn;
     cur = nxt;
@@ -792,18 +907,24 @@ hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* co
   }
   // evenly tiled by 256 rows, three parts: the wide persistent tiles, one
   // workgroup per CU (measured at 256^3: 109 us against 116 us for the
-  // single-buffered 128 x 128 tiles below)
-  if (parts == 3 && aligned && n % 256 == 0 && X % 128 == 0) {
+  // single-buffered 128 x 128 tiles below); their epilogue stores 16-byte
+  // pieces of out (and reads Y, Z so), which must then be 16-byte aligned too
+  bool wide = parts == 3 && aligned && n % 256 == 0 && X % 128 == 0;
+  for (int g = 0; wide && g < group; ++g)
+    wide = reinterpret_cast<uintptr_t>(out[g]) % 16 == 0 &&
+           !(Y && Y[g] && reinterpret_cast<uintptr_t>(Y[g]) % 16) &&
+           !(Z && Z[g] && reinterpret_cast<uintptr_t>(Z[g]) % 16);
+  if (wide) {
     const long long ntiles = (long long)group * (n / 256) * (X / 128);
     if (ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
     const int grid = (int)std::min<long long>(ntiles, lowp_cu_count());
     const int n_itiles = n / 256, n_xtiles = (int)(X / 128);
     if (out_f64)
-      hipLaunchKernelGGL((k_tgemm_bf16s_wide<3, true>), dim3(grid), dim3(512), 0, s, a, n_itiles,
-                         n_xtiles, (int)ntiles);
+      hipLaunchKernelGGL((k_tgemm_bf16s_wide<3, kOutF64>), dim3(grid), dim3(512), 0, s, a,
+                         n_itiles, n_xtiles, (int)ntiles);
     else
-      hipLaunchKernelGGL((k_tgemm_bf16s_wide<3, false>), dim3(grid), dim3(512), 0, s, a, n_itiles,
-                         n_xtiles, (int)ntiles);
+      hipLaunchKernelGGL((k_tgemm_bf16s_wide<3, kOutF32>), dim3(grid), dim3(512), 0, s, a,
+                         n_itiles, n_xtiles, (int)ntiles);
     return hipGetLastError();
   }
   // evenly tiled by 128 with enough tiles: 128 x 128 tiles with one LDS buffer,
