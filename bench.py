@@ -40,6 +40,7 @@ sys.path.insert(0, ROOT)
 METRIC = "grid-point-steps/s at 256³ (FP64 vs split-BF16/FP32) + p50/p99 solve latency"
 PEAKS = {  # published MI355X dense peaks
     "f64_mfma_tflops": 78.6,
+    "f64_vector_tflops": 78.6,
     "f32_mfma_tflops": 157.3,
     "bf16_mfma_tflops": 2500.0,
     "hbm_gbs": 8000.0,
@@ -268,6 +269,19 @@ def _lowp_roofline(prec, w, avg_ms, launches, fused_avg_ms):
     return rec
 
 
+def _whole_step_record(w, steps, launches, ms):
+    """The launch that runs every step of a small 2D FP64 problem: its product
+    flops (8 sum(n_mu) N per step, FP64 FMAs on the vector units) against the
+    FP64 vector peak.  At 4096 points it is bound by the latency of its two grid
+    barriers per step, not by arithmetic."""
+    flops = 8.0 * sum(w.n) * w.N * steps
+    tf = flops / (ms * 1e-3) / 1e12
+    return {"kernel": "etd_small2d (all steps in one cooperative launch)", "bound": "alu",
+            "launches": launches, "steps": steps, "ms_per_step": ms / steps,
+            "achieved": tf, "peak": PEAKS["f64_vector_tflops"], "unit": "TFLOP/s",
+            "frac": tf / PEAKS["f64_vector_tflops"], "flops_per_launch": flops / launches}
+
+
 def _workload_legs(adr, S, torch, seed, with_oracle=True):
     """The other two model workloads at one GPU, FP64: the 2D Schnakenberg 64^2
     (launch-bound at 4096 points) and the 3D FitzHugh-Nagumo 128^3, with the mode
@@ -301,6 +315,7 @@ def _workload_legs(adr, S, torch, seed, with_oracle=True):
         torch.cuda.synchronize()
         n_mode, ms_mode = adr.adr_timing_read(0)
         n_fused, ms_fused = adr.adr_timing_read(3)
+        n_whole, ms_whole = adr.adr_timing_read(4)
         n_all, ms_all = adr.adr_timing_read(2)
         adr.adr_timing_enable(0)
         # mode-product flops of a step: 4 Tucker operators, 2 components, 2 n_mu N each
@@ -310,11 +325,14 @@ def _workload_legs(adr, S, torch, seed, with_oracle=True):
         leg = {"grid": list(w.n), "steps": steps, "value": w.N * steps / dt,
                "ms_per_step": 1e3 * dt / steps,
                "rel_inf_err_vs_oracle": err, "oracle_steps": osteps if with_oracle else None,
-               "mode_products": {"launches_per_step": (n_mode + n_fused) / steps,
-                                 "ms_per_step": ms_products / steps,
-                                 "tflops": tf, "peak": PEAKS["f64_mfma_tflops"],
-                                 "frac": tf / PEAKS["f64_mfma_tflops"] if tf else None},
+               "mode_products": None if tf is None else {
+                   "launches_per_step": (n_mode + n_fused) / steps,
+                   "ms_per_step": ms_products / steps,
+                   "tflops": tf, "peak": PEAKS["f64_mfma_tflops"],
+                   "frac": tf / PEAKS["f64_mfma_tflops"]},
                "kernel_ms_per_step": ms_all / steps}
+        if n_whole:
+            leg["whole_step_kernel"] = _whole_step_record(w, steps, n_whole, ms_whole)
         if name == "schnakenberg2d_64":
             Ub, Vb = solver.upload(U0, V0)
             b = adr.Batch([solver], [(Ub, Vb)], adr.ADR_BATCH_GRAPH)
@@ -504,6 +522,7 @@ def main(argv=None):
     n_mode, ms_mode = adr.adr_timing_read(0)
     n_stage, ms_stage = adr.adr_timing_read(1)
     n_fused, ms_fused = adr.adr_timing_read(3)
+    n_whole, ms_whole = adr.adr_timing_read(4)
     adr.adr_timing_enable(0)
 
     # ---- the oracle on the host's cores: a bounded, timed sample of the same
@@ -550,7 +569,13 @@ def main(argv=None):
     # (16 B) and writes R2 (16 B); reduced precision reads C_n (16 B) and D1 (8 B) and
     # writes FP64 instead of FP32 (8 B)
     fused_avg_ms = ms_fused / n_fused if n_fused else None
-    if args.precision == "f64":
+    if n_whole and not n_mode:
+        # small 2D grids: every step in one launch (stages and products together)
+        roof = _whole_step_record(w, args.steps, n_whole, ms_whole)
+        roof["avg_launch_ms"] = ms_whole / n_whole
+        roof["traffic"] = None
+        bytes_per_launch = None
+    elif args.precision == "f64":
         achieved = flops_per_launch / (mode_avg_ms * 1e-3) / 1e12
         bytes_per_launch = 2 * 2 * 8 * N  # read + write one tensor per component
         roof = {"kernel": "mode_product_f64", "bound": "mfma", "achieved": achieved,
@@ -562,9 +587,10 @@ def main(argv=None):
     else:
         roof = _lowp_roofline(args.precision, w, mode_avg_ms, n_mode, fused_avg_ms)
         bytes_per_launch = roof["algorithmic_bytes_per_launch"]
-    roof["tflops"] = flops_per_launch / (mode_avg_ms * 1e-3) / 1e12
-    roof["traffic"] = _traffic_from_profiles(args.precision, w.name)
-    fused_bytes = bytes_per_launch + 32 * N
+    if n_mode:
+        roof["tflops"] = flops_per_launch / (mode_avg_ms * 1e-3) / 1e12
+        roof["traffic"] = _traffic_from_profiles(args.precision, w.name)
+    fused_bytes = None if bytes_per_launch is None else bytes_per_launch + 32 * N
     roof["fused_launch"] = None if fused_avg_ms is None else {
         "what": ("last product of the phi_1 operator, stage 2 in its epilogue"
                  if args.precision == "f64" else
@@ -604,7 +630,7 @@ def main(argv=None):
                    "precision": args.precision, "tau": w.tau, "seed": args.seed,
                    "model": model_text},
         "roofline": roof,
-        "stage_kernels": {
+        "stage_kernels": None if not n_stage else {
             "bound": "hbm",
             "avg_launch_ms": stage_avg_ms,
             "achieved": stage_bytes / (stage_avg_ms * 1e-3) / 1e9,

@@ -186,8 +186,13 @@ size_t adr_workspace_bytes(const adr_problem* p);
  *   U, V   device, N doubles each (FP64 state in every precision mode)
  *   work   device, at least adr_workspace_bytes(p) bytes, 256-byte aligned
  * Enqueues 2*d mode-product launches and 2 stage launches (ETD2RKds) on
- * `stream`; no synchronisation.  Errors: ADR_EINVAL, ADR_ENOMEM (work too
- * small), ADR_ENOTSUP, ADR_EDEVICE.
+ * `stream`; no synchronisation.  FP64 ETD2RKds on 2D grids of 64 x n2
+ * (3 <= n2 <= 64) with tridiagonal operators (band given) and 16-byte aligned
+ * direction-1 matrices instead runs all steps of the call in one cooperative
+ * launch (after a one-thread reset of its barrier counter); should that
+ * launch ever abandon its steps (a grid barrier that does not complete within
+ * its spin limit), U and V are left NaN on the abandoned columns.  Errors:
+ * ADR_EINVAL, ADR_ENOMEM (work too small), ADR_ENOTSUP, ADR_EDEVICE.
  */
 int adr_step(const adr_problem* p, double* U, double* V, void* work, size_t work_bytes,
              void* stream);
@@ -342,8 +347,9 @@ int adr_batch_destroy(adr_batch* plan);
  * adr_timing_read synchronises on the recorded events and returns, for the
  * kernel class `kind` (0 = mode products, 1 = stage kernels, 2 = all,
  * 3 = mode products whose epilogue also computes a stage: ETD2RKds stage 2 in
- * FP64, the new state in reduced precision), the number of launches and their
- * summed duration in milliseconds.  The record is kept until the next
+ * FP64, the new state in reduced precision, 4 = launches that run whole steps:
+ * FP64 ETD2RKds on 2D grids of 64 x n2, 3 <= n2 <= 64, with tridiagonal
+ * operators), the number of launches and their summed duration in milliseconds.  The record is kept until the next
  * adr_timing_enable.  Not thread-safe; intended for benchmarks.
  */
 int adr_timing_enable(int capacity);

@@ -444,6 +444,21 @@ hipError_t step_lawson2b(const adr_problem* p, const Geometry& g, const Carve& c
   });
 }
 
+// Small 2D FP64 ETD2RKds problems with tridiagonal operators run whole steps
+// in one cooperative launch (launch_etd_small2d).
+bool small2d_step(const adr_problem* p, const Geometry& g) {
+  if (p->scheme != ADR_ETD2RKDS || p->precision != ADR_F64 || !small2d_fits(g.d, g.n[0], g.n[1]))
+    return false;
+  for (int cc = 0; cc < 2; ++cc) {
+    for (int mu = 0; mu < 2; ++mu)
+      if (!p->band[cc][mu]) return false;
+    // the direction-1 matrices are copied into LDS in 16-byte pieces
+    for (int j = 1; j <= 2; ++j)
+      if (reinterpret_cast<uintptr_t>(p->phi[cc][j][0]) % 16 != 0) return false;
+  }
+  return true;
+}
+
 int do_steps(const adr_problem* p, double* U, double* V, int nsteps, void* work,
              size_t work_bytes, void* stream) {
   Geometry g{};
@@ -459,6 +474,31 @@ int do_steps(const adr_problem* p, double* U, double* V, int nsteps, void* work,
         if (!p->band[cc][mu]) return ADR_ENOTSUP;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Carve c = carve(p, g, static_cast<char*>(work));
+  if (small2d_step(p, g) && nsteps > 0) {
+    // every step in one cooperative launch; the exchange buffers are the
+    // stage buffers of the launch-by-launch path, its barrier counter and
+    // error flag the first 8 bytes of U2
+    Small2dArgs a{};
+    a.U = U;
+    a.V = V;
+    for (int cc = 0; cc < 2; ++cc) {
+      for (int op = 0; op < 2; ++op) {
+        a.P1[op][cc] = p->phi[cc][1 + op][0];
+        a.P2[op][cc] = p->phi[cc][1 + op][1];
+      }
+      a.band[cc][0] = p->band[cc][0];
+      a.band[cc][1] = p->band[cc][1];
+      a.Y[0][cc] = static_cast<double*>(c.R[cc]);
+      a.Y[1][cc] = static_cast<double*>(c.T[cc]);
+    }
+    a.r = reaction_of(p);
+    a.tau = p->tau;
+    a.n2 = g.n[1];
+    a.counter = reinterpret_cast<unsigned*>(c.U2);
+    a.err = reinterpret_cast<int*>(c.U2) + 1;
+    const hipError_t e = timed(kKindSteps, s, [&] { return launch_etd_small2d(a, nsteps, s); });
+    return e == hipSuccess ? ADR_OK : ADR_EDEVICE;
+  }
   hipError_t e = prepare_lowp(p, g, c, s);
   if (e != hipSuccess) return ADR_EDEVICE;
   for (int it = 0; it < nsteps; ++it) {
@@ -922,7 +962,7 @@ int adr_timing_enable(int capacity) {
 }
 
 int adr_timing_read(int kind, int* launches, double* total_ms) {
-  if (!launches || !total_ms || kind < 0 || kind > 3) return ADR_EINVAL;
+  if (!launches || !total_ms || kind < 0 || kind > 4) return ADR_EINVAL;
   Timing& t = g_timing;
   int cnt = 0;
   double tot = 0.0;

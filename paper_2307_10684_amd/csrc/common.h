@@ -174,6 +174,26 @@ hipError_t launch_etd_stage2(long long N, const Reaction& r, const double* U, co
 hipError_t launch_etd_stage2_inc(long long N, const Reaction& r, const double* U, const double* V,
                                  const float* Du, const float* Dv, float* Ru, float* Rv,
                                  hipStream_t s);
+// Whole FP64 ETD2RKds steps of a small 2D problem (n1 = 64, 3 <= n2 <= 64,
+// tridiagonal operators) in one cooperative launch, the state updated in place.
+// P1/P2[op][c]: the direction-1 / direction-2 matrices of component c for
+// op 0 (phi_1) and op 1 (phi_2); band[c][mu] as in adr_problem; Y[op][c]:
+// n1 x n2 doubles of workspace each; counter, err: a 4-byte slot each.
+struct Small2dArgs {
+  double* U;
+  double* V;
+  const double* P1[2][2];
+  const double* P2[2][2];
+  const double* band[2][2];
+  Reaction r;
+  double tau;
+  int n2;
+  double* Y[2][2];
+  unsigned* counter;
+  int* err;
+};
+bool small2d_fits(int d, int n1, int n2);
+hipError_t launch_etd_small2d(const Small2dArgs& a, int nsteps, hipStream_t s);
 // Lawson2b stage 1: A^c = C + tau G^c(U, V), B^c = C + tau/2 G^c(U, V).
 hipError_t launch_lawson_stage1(long long N, const Reaction& r, double tau, const double* U,
                                 const double* V, void* Au, void* Av, void* Bu, void* Bv, int f32,

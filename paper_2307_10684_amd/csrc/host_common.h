@@ -42,7 +42,7 @@ hipError_t timed(int kind, hipStream_t s, F&& f) {
 }
 // timing classes: plain mode products, stage kernels, and mode products whose
 // epilogue also carries a stage (ETD2RKds stage 2, or the new state)
-constexpr int kKindMode = 0, kKindStage = 1, kKindModeFused = 3;
+constexpr int kKindMode = 0, kKindStage = 1, kKindModeFused = 3, kKindSteps = 4;
 
 
 inline int dev_err(hipError_t e) { return e == hipSuccess ? ADR_OK : ADR_EDEVICE; }

@@ -167,7 +167,8 @@ def test_other_entry_points_validate(adr):
     for kind in range(4):
         assert lib.adr_timing_read(kind, ctypes.byref(cnt), ctypes.byref(tot)) == adr.ADR_OK
         assert cnt.value == 0 and tot.value == 0.0
-    assert lib.adr_timing_read(4, ctypes.byref(cnt), ctypes.byref(tot)) == adr.ADR_EINVAL
+    assert lib.adr_timing_read(5, ctypes.byref(cnt), ctypes.byref(tot)) == adr.ADR_EINVAL
+    assert lib.adr_timing_read(4, ctypes.byref(cnt), ctypes.byref(tot)) == adr.ADR_OK
     assert lib.adr_timing_read(-1, ctypes.byref(cnt), ctypes.byref(tot)) == adr.ADR_EINVAL
 
 

@@ -51,7 +51,7 @@ def test_source_hash_ignores_comments_and_blank_lines(tmp_path, monkeypatch):
 @pytest.mark.parametrize("precision,workload", [
     ("f64", "brusselator3d_256"), ("f32", "brusselator3d_256"), ("bf16x3", "brusselator3d_256"),
     ("bf16x2", "brusselator3d_256"),
-    ("f64", "fhn3d_128"), ("f64", "schnakenberg2d_64")])
+    ("f64", "fhn3d_128")])
 def test_committed_counter_summaries_match_the_kernel_sources(precision, workload):
     # a summary taken before the kernel's code last changed is ignored by bench.py
     # (traffic null); the committed ones must be current
@@ -94,3 +94,15 @@ def test_reduced_precision_roofline_bounds():
     r2 = bench._lowp_roofline("bf16x2", w, 0.085, 100, None)
     assert r2["bound"] == "hbm" and r2["peak"] == bench.PEAKS["hbm_gbs"]
     assert 0 < r2["frac"] < 1
+
+
+def test_whole_step_record():
+    # the 64^2 FP64 step runs as one launch: its record prices the products'
+    # 8 sum(n_mu) N flops per step against the FP64 vector peak
+    w = S.schnakenberg_2d(64, 10)
+    rec = bench._whole_step_record(w, 400, 1, 4.0)
+    flops = 8.0 * 128 * 4096 * 400
+    assert rec["bound"] == "alu" and rec["peak"] == bench.PEAKS["f64_vector_tflops"]
+    assert abs(rec["achieved"] - flops / 4e-3 / 1e12) < 1e-12
+    assert abs(rec["frac"] - rec["achieved"] / 78.6) < 1e-15
+    assert abs(rec["ms_per_step"] - 0.01) < 1e-15

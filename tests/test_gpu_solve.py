@@ -86,6 +86,13 @@ CASES = [
     # 3D grids of 2^20 points or more with n1 = 64 or 256: stage 1 by whole-row waves
     ("fhn3d_64x128x128_5", S.with_shape(S.fhn_3d(), (64, 128, 128)), 5),
     ("bruss3d_256x64x72_3", S.with_shape(S.brusselator_3d(), (256, 64, 72)), 3),
+    # 2D grids of 64 x n2 (n2 <= 64): every step in one cooperative launch, four
+    # columns per workgroup; a last workgroup with fewer columns (30, 3), the
+    # advective Brusselator (non-symmetric bands) and the DIB model
+    ("schnakenberg2d_64x30_40", S.with_shape(S.schnakenberg_2d(), (64, 30)), 40),
+    ("fhn2d_64x3_20", S.with_shape(S.fhn_3d(), (64, 3)), 20),
+    ("bruss2d_64x64_30", S.with_shape(S.brusselator_3d(), (64, 64)), 30),
+    ("dib2d_64x48_20", S.with_shape(S.dib_2d(200, 1250), (64, 48)), 20),
 ]
 
 
@@ -153,6 +160,16 @@ def test_bitwise_determinism_and_resume(dev):
     c = _gpu(dev, w, U0, V0, 20, chunks=[7, 13])
     for x, y, z in zip(a, b, c):
         assert np.array_equal(x, y) and np.array_equal(x, z)
+
+
+def test_whole_step_launch_resumes_bitwise(dev):
+    # the 64 x n2 path runs a solve call's steps in one launch; splitting the
+    # steps over several calls gives the same bits
+    w = S.with_shape(S.brusselator_3d(), (64, 40))
+    U0, V0 = S.initial_state(w, 6)
+    a = _gpu(dev, w, U0, V0, 30)
+    b = _gpu(dev, w, U0, V0, 30, chunks=[1, 7, 22])
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
 @pytest.mark.parametrize("w", [S.schnakenberg_2d(64, 1), S.fhn_3d(48, 1), S.brusselator_3d(40, 1)],
