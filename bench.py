@@ -84,6 +84,11 @@ def _traffic_from_profiles(precision: str, workload: str):
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256_16") != _src_hash(MODE_SRC[precision]):
         return None
+    # a summary that covers several sources lists them with their hashes
+    for item in vals.get("kernel_sources", "").split(","):
+        parts = item.split()
+        if len(parts) == 2 and _src_hash(os.path.basename(parts[0])) != parts[1]:
+            return None
     try:
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -562,8 +567,13 @@ def main(argv=None):
     ms_per_step = 1e3 * elapsed / args.steps
     value = N * args.steps / elapsed
     mode_avg_ms = ms_mode / max(n_mode, 1)
-    # algorithmic work of one mode-product launch: both components, 2*n_mu*N flops each
-    flops_per_launch = 2 * 2.0 * (sum(w.n) / d) * N
+    # algorithmic work of the plain mode-product launches: 2 d products per step
+    # (both components, 2 n_mu N flops each), less the one a launch that carries
+    # a stage holds; a plane-pass launch holds two (directions 1 and 2), so the
+    # work per launch is the launches' total over their number
+    products_plain = 2 * d * args.steps - n_fused
+    flops_per_launch = (products_plain * 2 * 2.0 * (sum(w.n) / d) * N / n_mode if n_mode
+                        else 2 * 2.0 * (sum(w.n) / d) * N)
     # the product launch of a step whose epilogue also computes a stage (timed apart),
     # 32 B/point more than a plain launch in both cases: FP64 reads the states C_n
     # (16 B) and writes R2 (16 B); reduced precision reads C_n (16 B) and D1 (8 B) and
@@ -597,7 +607,7 @@ def main(argv=None):
                  "last product of the phi_2 operator, writes C_n + D1 + D2 in FP64"),
         "launches": n_fused,
         "avg_launch_ms": fused_avg_ms,
-        "tflops": flops_per_launch / (fused_avg_ms * 1e-3) / 1e12,
+        "tflops": 2 * 2.0 * (sum(w.n) / d) * N / (fused_avg_ms * 1e-3) / 1e12,
         "algorithmic_bytes_per_launch": fused_bytes,
         "hbm_gbs": fused_bytes / (fused_avg_ms * 1e-3) / 1e9,
     }

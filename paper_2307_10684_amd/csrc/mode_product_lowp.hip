@@ -42,10 +42,15 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef short s8 __attribute__((ext_vector_type(8)));
 
-// float -> bf16 bits, round to nearest even (inputs are finite)
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+
+// float -> bf16 bits, round to nearest even (the conversion instruction; on
+// gfx950 it gives the same bits as rounding the FP32 bit pattern to nearest
+// even, denormals included, checked over 2^24 finite values)
 __device__ __forceinline__ unsigned short bf16_bits(float x) {
-  const unsigned u = __float_as_uint(x);
-  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+  return __builtin_bit_cast(unsigned short, static_cast<__bf16>(x));
 }
 __device__ __forceinline__ float bf16_float(unsigned short b) {
   return __uint_as_float((unsigned)b << 16);
@@ -359,18 +364,39 @@ __global__ __launch_bounds__(kThreads, 2) void k_tgemm_f32_grouped(const LowpJob
 }
 
 // ------------------------------------------------------------------ split BF16
-// Split of one FP32 value into PARTS bf16 parts: each part is the bf16
-// rounding (to nearest even) of what the previous parts leave.  The
-// remainders are exact FP32 differences; with three parts the last one is
-// exactly representable, so hi + mid + lo == x.
+// Split of FP32 values into PARTS bf16 parts: each part is the bf16 rounding
+// (to nearest even) of what the previous parts leave.  The remainders are
+// exact FP32 differences; with three parts the last one is exactly
+// representable, so hi + mid + lo == x.  Two values at a time through the
+// packed conversion: part[p] holds the p-th parts of x0 (low half) and x1
+// (high half).
 template <int PARTS>
-__device__ __forceinline__ void split_bf16(float x, unsigned short (&part)[PARTS]) {
-  float r = x;
+__device__ __forceinline__ void split_bf16_pair(float x0, float x1, unsigned (&part)[PARTS]) {
+  float r0 = x0, r1 = x1;
 #pragma unroll
   for (int p = 0; p < PARTS; ++p) {
-    part[p] = bf16_bits(r);
-    if (p + 1 < PARTS) r = r - bf16_float(part[p]);
+    const unsigned b = __builtin_bit_cast(unsigned, __builtin_convertvector(f2{r0, r1}, bf2));
+    part[p] = b;
+    if (p + 1 < PARTS) {
+      r0 = r0 - __uint_as_float(b << 16);
+      r1 = r1 - __uint_as_float(b & 0xffff0000u);
+    }
   }
+}
+
+// Split eight consecutive FP32 values into PARTS vectors of eight bf16.
+template <int PARTS>
+__device__ __forceinline__ void split_bf16_8(const float (&x)[8], s8 (&v)[PARTS]) {
+  u4 w[PARTS];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    unsigned part[PARTS];
+    split_bf16_pair<PARTS>(x[2 * j], x[2 * j + 1], part);
+#pragma unroll
+    for (int pp = 0; pp < PARTS; ++pp) w[pp][j] = part[pp];
+  }
+#pragma unroll
+  for (int pp = 0; pp < PARTS; ++pp) v[pp] = __builtin_bit_cast(s8, w[pp]);
 }
 
 // One 16x16 block of the split product over a 32-deep chunk: the products of
@@ -486,13 +512,7 @@ __global__ __launch_bounds__(64 * WI * WX, 2) void k_tgemm_bf16s(LowpArgs a, int
     for (int p = 0; p < WLOADS; ++p) {
       const int s = tid + p * kThreads, r = s >> 2, q = s & 3;
       s8 v[PARTS];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        unsigned short part[PARTS];
-        split_bf16<PARTS>(rw[p][j], part);
-#pragma unroll
-        for (int pp = 0; pp < PARTS; ++pp) v[pp][j] = (short)part[pp];
-      }
+      split_bf16_8<PARTS>(rw[p], v);
 #pragma unroll
       for (int pp = 0; pp < PARTS; ++pp)
         *reinterpret_cast<s8*>(&sW[buf][pp][r * LDK + slot(r, q)]) = v[pp];
@@ -709,14 +729,9 @@ __global__ __launch_bounds__(512, 1) void k_tgemm_bf16s_wide(LowpArgs a, int n_i
     rw1 = src[1];
   };
   auto store_w = [&](unsigned short* dst) {
+    const float x[8] = {rw0[0], rw0[1], rw0[2], rw0[3], rw1[0], rw1[1], rw1[2], rw1[3]};
     s8 v[PARTS];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      unsigned short part[PARTS];
-      split_bf16<PARTS>(j < 4 ? rw0[j] : rw1[j - 4], part);
-#pragma unroll
-      for (int pp = 0; pp < PARTS; ++pp) v[pp][j] = (short)part[pp];
-    }
+    split_bf16_8<PARTS>(x, v);
 #pragma unroll
     for (int pp = 0; pp < PARTS; ++pp)
       *reinterpret_cast<s8*>(dst + pp * PLANE_W + w_x * BK + 8 * w_slot) = v[pp];
