@@ -13,10 +13,13 @@
 // chunks of 16 columns (they are small and stay in L2).
 //
 // LDS layout of the plane: column c (the i2 index) holds rows r (i1) at
-// c * N + (r ^ 2 (c % 16)); the permutation keeps pairs of consecutive rows
-// together (it only changes the bits above the lowest one) and sends the 16
-// consecutive columns of a fragment read (fixed r) to 16 different double
-// slots, so those reads are free of bank conflicts.
+// c * N + (r ^ (c % 16)); the permutation sends the 16 consecutive columns of
+// a fragment read (fixed r) to 16 different double slots of a 128-byte bank
+// window, so those reads and the stores of the products' results are free of
+// bank conflicts.  (Keeping row pairs together for 16-byte LDS-direct loads
+// allows only even masks, 8 distinct slots and two-way conflicts; the plane
+// is therefore copied with 4-byte LDS-direct loads, each lane choosing the
+// half of the double its LDS word holds.)
 //
 // FP64 MFMA fragments (v_mfma_f64_16x16x4f64): A[l%16][l/16], B[l/16][l%16],
 // D[4v + l/16][l%16], v = 0..3.
@@ -40,7 +43,7 @@ struct PlaneArgs {
 
 template <int N>
 __device__ __forceinline__ int pidx(int r, int c) {
-  return c * N + (r ^ (2 * (c & 15)));
+  return c * N + (r ^ (c & 15));
 }
 
 // 16 KB (N = 128) or 8 KB (N = 64) of a chunk: 16 whole columns of M, contiguous
@@ -57,18 +60,21 @@ __device__ __forceinline__ void dma_chunk(double* dst, const double* __restrict_
   }
 }
 
-// The plane: each wave instruction fills 128 consecutive LDS doubles; lane l
-// fills positions 2l, 2l+1 of them with rows (q ^ 2(c % 16)), q its position in
-// the column (the pair stays consecutive).
+// The plane: each wave instruction fills 32 consecutive LDS doubles (256
+// bytes, 4 per lane); lane l fills the low (l even) or high (l odd) word of
+// position l / 2 of them with the same word of row (q ^ (c % 16)), q the
+// position in column c.  The 32 rows of one instruction are a permutation of
+// an aligned block of 32 rows, so each instruction reads 256 contiguous bytes.
 template <int N, int NW>
 __device__ __forceinline__ void dma_plane(double* P, const double* __restrict__ W, int wave) {
-  constexpr int PSPANS = N * N / 128;
+  constexpr int PSPANS = N * N / 32;
   const int lane = threadIdx.x & 63;
-#pragma unroll 4
+#pragma unroll 8
   for (int s = wave; s < PSPANS; s += NW) {
-    const int e = s * 128 + 2 * lane;
+    const int e = s * 32 + (lane >> 1);
     const int c = e / N, q = e % N;
-    __builtin_amdgcn_global_load_lds(W + (size_t)c * N + (q ^ (2 * (c & 15))), P + s * 128, 16, 0, 0);
+    const char* src = reinterpret_cast<const char*>(W + (size_t)c * N + (q ^ (c & 15))) + 4 * (lane & 1);
+    __builtin_amdgcn_global_load_lds(src, P + s * 32, 4, 0, 0);
   }
 }
 
@@ -176,7 +182,7 @@ __global__ __launch_bounds__(64 * WI * WX, 1) void k_mode12_plane(PlaneArgs a) {
 #pragma unroll 4
   for (int e = 2 * tid; e < N * N; e += 2 * NT) {
     const int c = e / N, r = e % N;
-    const d2 z = *reinterpret_cast<const d2*>(&P[pidx<N>(r, c)]);
+    const d2 z = {P[pidx<N>(r, c)], P[pidx<N>(r + 1, c)]};
     d2 o = {alpha * z[0], alpha * z[1]};
     if (Yp) {
       const d2 y = *reinterpret_cast<const d2*>(Yp + e);
