@@ -191,7 +191,9 @@ size_t adr_workspace_bytes(const adr_problem* p);
  * direction-1 matrices instead runs all steps of the call in one cooperative
  * launch (after a one-thread reset of its barrier counter); should that
  * launch ever abandon its steps (a grid barrier that does not complete within
- * its spin limit), U and V are left NaN on the abandoned columns.  Errors:
+ * its spin limit, about 2^20 polls; the environment variable
+ * ADR_TEST_SPIN_LIMIT lowers it, for tests of this path), U and V are left NaN
+ * on the abandoned columns.  Errors:
  * ADR_EINVAL, ADR_ENOMEM (work too small), ADR_ENOTSUP, ADR_EDEVICE.
  */
 int adr_step(const adr_problem* p, double* U, double* V, void* work, size_t work_bytes,

@@ -496,6 +496,7 @@ int do_steps(const adr_problem* p, double* U, double* V, int nsteps, void* work,
     a.n2 = g.n[1];
     a.counter = reinterpret_cast<unsigned*>(c.U2);
     a.err = reinterpret_cast<int*>(c.U2) + 1;
+    a.spin_limit = small2d_spin_limit();
     const hipError_t e = timed(kKindSteps, s, [&] { return launch_etd_small2d(a, nsteps, s); });
     return e == hipSuccess ? ADR_OK : ADR_EDEVICE;
   }

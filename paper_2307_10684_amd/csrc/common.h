@@ -191,8 +191,13 @@ struct Small2dArgs {
   double* Y[2][2];
   unsigned* counter;
   int* err;
+  unsigned spin_limit;      // polls before a barrier wait gives up
 };
 bool small2d_fits(int d, int n1, int n2);
+// Polls a whole-step barrier allows before the launch is abandoned: about 2^20,
+// or the value of the environment variable ADR_TEST_SPIN_LIMIT when it is set
+// (for tests of the abandon path).
+unsigned small2d_spin_limit();
 hipError_t launch_etd_small2d(const Small2dArgs& a, int nsteps, hipStream_t s);
 // Lawson2b stage 1: A^c = C + tau G^c(U, V), B^c = C + tau/2 G^c(U, V).
 hipError_t launch_lawson_stage1(long long N, const Reaction& r, double tau, const double* U,

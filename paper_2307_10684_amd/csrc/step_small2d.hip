@@ -51,10 +51,12 @@
 // the workgroup barrier then releases the other waves, whose exchange loads
 // are issued after it.  The launch is cooperative, so every workgroup is
 // resident and every barrier completes; the wait is still bounded: after
-// kSpinLimit polls a workgroup raises the shared error flag, every
+// kSpinLimit polls (fewer when the host says so, for tests of this path) a
+// workgroup raises the shared error flag, every
 // workgroup leaves at its next barrier, and the own columns of U and V are
 // filled with NaN, so an incomplete launch cannot pass for a result.
 #include <cmath>
+#include <cstdlib>
 
 #include "common.h"
 #include "reaction.h"
@@ -77,7 +79,8 @@ __global__ void k_zero_sync(unsigned* counter, int* err) {
 
 // Grid barrier: returns false when the launch is being abandoned (a barrier
 // timed out in some workgroup).
-__device__ __forceinline__ bool grid_sync(unsigned* counter, int* err, unsigned target, int* sflag) {
+__device__ __forceinline__ bool grid_sync(unsigned* counter, int* err, unsigned target,
+                                          unsigned spin_limit, int* sflag) {
   __builtin_amdgcn_s_waitcnt(0);   // this wave's exchange stores have completed
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -86,7 +89,7 @@ __device__ __forceinline__ bool grid_sync(unsigned* counter, int* err, unsigned 
     unsigned spins = 0;
     while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-          ++spins > kSpinLimit) {
+          ++spins > spin_limit) {
         failed = 1;
         break;
       }
@@ -258,7 +261,7 @@ __global__ __launch_bounds__(512, 1) void k_etd_small2d(Small2dArgs a, int nstep
     stage(true);
     __syncthreads();
     dir1(a.Y[0]);
-    if (!(ok = grid_sync(a.counter, a.err, G * ++bar, &sflag))) break;
+    if (!(ok = grid_sync(a.counter, a.err, G * ++bar, a.spin_limit, &sflag))) break;
     // ---- P2, with operator 1's direction-1 matrices in flight (the copy is
     // issued first: its loads hit in L2, the exchange loads do not)
     {
@@ -278,7 +281,7 @@ __global__ __launch_bounds__(512, 1) void k_etd_small2d(Small2dArgs a, int nstep
     __builtin_amdgcn_s_waitcnt(0);   // this wave's part of the matrix copy has landed
     __syncthreads();
     dir1(a.Y[1]);
-    if (!(ok = grid_sync(a.counter, a.err, G * ++bar, &sflag))) break;
+    if (!(ok = grid_sync(a.counter, a.err, G * ++bar, a.spin_limit, &sflag))) break;
     // ---- P4, with operator 0's direction-1 matrices in flight for the next step
     {
       double y[16], z[2];
@@ -304,6 +307,14 @@ __global__ __launch_bounds__(512, 1) void k_etd_small2d(Small2dArgs a, int nstep
 }
 
 }  // namespace
+
+unsigned small2d_spin_limit() {
+  const char* v = std::getenv("ADR_TEST_SPIN_LIMIT");
+  if (!v || !*v) return kSpinLimit;
+  char* end = nullptr;
+  const unsigned long x = std::strtoul(v, &end, 10);
+  return (end && *end == '\0' && x < kSpinLimit) ? (unsigned)x : kSpinLimit;
+}
 
 bool small2d_fits(int d, int n1, int n2) {
   return d == 2 && n1 == kN1 && n2 >= 3 && n2 <= kMaxN2;

@@ -162,6 +162,19 @@ def test_bitwise_determinism_and_resume(dev):
         assert np.array_equal(x, y) and np.array_equal(x, z)
 
 
+def test_whole_step_launch_abandons_to_nan(dev, monkeypatch):
+    # a grid barrier that gives up (forced here by a spin limit of 0 polls, set
+    # from the host) ends the launch with NaN in U and V instead of a result,
+    # and the next call with the normal limit steps correctly again
+    w = S.with_shape(S.schnakenberg_2d(), (64, 64))
+    U0, V0, U, V, mats = _oracle(w, 7, 10)
+    monkeypatch.setenv("ADR_TEST_SPIN_LIMIT", "0")
+    bad = _gpu(dev, w, U0, V0, 10, mats=mats)
+    assert np.isnan(bad[0]).all() and np.isnan(bad[1]).all()
+    monkeypatch.delenv("ADR_TEST_SPIN_LIMIT")
+    _assert_close(_gpu(dev, w, U0, V0, 10, mats=mats), (U, V))
+
+
 def test_whole_step_launch_resumes_bitwise(dev):
     # the 64 x n2 path runs a solve call's steps in one launch; splitting the
     # steps over several calls gives the same bits
