@@ -87,7 +87,8 @@ __device__ __forceinline__ bool grid_sync(unsigned* counter, int* err, unsigned 
     __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int failed = 0;
     unsigned spins = 0;
-    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    // (wrap-safe: the counter and the targets run modulo 2^32 over long launches)
+    while ((int)(__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
       if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
           ++spins > spin_limit) {
         failed = 1;
