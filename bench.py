@@ -45,6 +45,7 @@ PEAKS = {  # published MI355X dense peaks
     "bf16_mfma_tflops": 2500.0,
     "hbm_gbs": 8000.0,
 }
+CHIP_CUS = 256   # compute units (the peaks above are for all of them)
 MODE_SRC = {"f64": "mode_product_f64.hip", "f32": "mode_product_lowp.hip",
             "bf16x3": "mode_product_lowp.hip", "bf16x2": "mode_product_lowp.hip"}
 # BF16 MFMA products per FP32-equivalent product of a split-BF16 precision:
@@ -281,10 +282,14 @@ def _whole_step_record(w, steps, launches, ms):
     barriers per step, not by arithmetic."""
     flops = 8.0 * sum(w.n) * w.N * steps
     tf = flops / (ms * 1e-3) / 1e12
+    # one workgroup of four columns per CU: the share of the chip the launch holds
+    cus = -(-int(w.n[1]) // 4)
+    own_peak = PEAKS["f64_vector_tflops"] * cus / CHIP_CUS
     return {"kernel": "etd_small2d (all steps in one cooperative launch)", "bound": "alu",
             "launches": launches, "steps": steps, "ms_per_step": ms / steps,
             "achieved": tf, "peak": PEAKS["f64_vector_tflops"], "unit": "TFLOP/s",
-            "frac": tf / PEAKS["f64_vector_tflops"], "flops_per_launch": flops / launches}
+            "frac": tf / PEAKS["f64_vector_tflops"], "flops_per_launch": flops / launches,
+            "cus": cus, "peak_of_own_cus": own_peak, "frac_of_own_cus": tf / own_peak}
 
 
 def _workload_legs(adr, S, torch, seed, with_oracle=True):

@@ -106,3 +106,6 @@ def test_whole_step_record():
     assert abs(rec["achieved"] - flops / 4e-3 / 1e12) < 1e-12
     assert abs(rec["frac"] - rec["achieved"] / 78.6) < 1e-15
     assert abs(rec["ms_per_step"] - 0.01) < 1e-15
+    # 64 columns, four per workgroup: 16 of the 256 CUs
+    assert rec["cus"] == 16
+    assert abs(rec["frac_of_own_cus"] - rec["achieved"] / (78.6 * 16 / 256)) < 1e-12
