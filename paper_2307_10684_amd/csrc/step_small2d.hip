@@ -29,8 +29,10 @@
 // overwrite what a slower one still reads (the barrier between them orders
 // every read before the next write).
 //
-// The products are FP64 FMAs on the vector units (at this size, and on this
-// chip, as fast per CU as the FP64 matrix instruction).  In each product the
+// The products are FP64 FMAs on the vector units: a workgroup's share is a
+// 64 x 64 matrix against 4 (direction 1) or 6 (direction 2) columns, too
+// narrow for 16 x 16 matrix-instruction blocks without padding, and a step's
+// time goes to its barriers and exchange loads, not to these FMAs.  In each product the
 // eight waves are (component c, quarter kq of the contraction index): lane i
 // forms row i's partial sums over its 16 values of k for every column, the
 // partial sums meet in LDS, and wave (c, q) adds the four quarters of its
