@@ -611,28 +611,32 @@ __device__ __forceinline__ void wide_epilogue(const LowpArgs& a, int g, const f4
     const double* Y = a.Y[g];
     const float* Z = a.Z[g];
     const double beta = a.beta;
-    d2 y[2][2];
-    f4 z[2];
+    // the addends of kDepth blocks ahead are in flight while a block is
+    // combined and stored
+    constexpr int kDepth = 4, kRing = kDepth + 1;
+    d2 y[kRing][2];
+    f4 z[kRing];
     // block b = (fx, fi) = (b / FI, b % FI)
     auto load = [&](int b) {
       const unsigned o = index(b / FI, b % FI);
       if (HASY) {
-        y[b & 1][0] = *reinterpret_cast<const d2*>(Y + o);
-        y[b & 1][1] = *reinterpret_cast<const d2*>(Y + o + 2);
+        y[b % kRing][0] = *reinterpret_cast<const d2*>(Y + o);
+        y[b % kRing][1] = *reinterpret_cast<const d2*>(Y + o + 2);
       }
-      if (HASZ) z[b & 1] = *reinterpret_cast<const f4*>(Z + o);
+      if (HASZ) z[b % kRing] = *reinterpret_cast<const f4*>(Z + o);
     };
-    load(0);
+#pragma unroll
+    for (int b = 0; b < kDepth && b < FX * FI; ++b) load(b);
 #pragma unroll
     for (int b = 0; b < FX * FI; ++b) {
-      if (b + 1 < FX * FI) load(b + 1);
+      if (b + kDepth < FX * FI) load(b + kDepth);
       const int fx = b / FI, fi = b % FI;
       double val[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const double p = alpha * (double)acc[fx][fi][v];
-        const double yv = HASY ? y[b & 1][v / 2][v % 2] : 0.0;
-        if (HASZ) val[v] = ((HASY ? beta * yv : 0.0) + (double)z[b & 1][v]) + p;
+        const double yv = HASY ? y[b % kRing][v / 2][v % 2] : 0.0;
+        if (HASZ) val[v] = ((HASY ? beta * yv : 0.0) + (double)z[b % kRing][v]) + p;
         else if (HASY) val[v] = p + beta * yv;
         else val[v] = p;
       }
@@ -718,6 +722,13 @@ __global__ __launch_bounds__(512, 1) void k_tgemm_bf16s_wide(LowpArgs a, int n_i
     for (int pp = 0; pp < PARTS; ++pp) planes[pp] = a.Mp[T.g][pp];
     dma_split_rows<PARTS, PLANE_M, 2>(dst, planes, (unsigned)T.i0, n, k0, 32 * wave);
   };
+  // half h (16 rows) of the wave's share of an M chunk
+  auto dma_m_half = [&](unsigned short* dst, const Tile& T, int k0, int h) {
+    const unsigned short* planes[PARTS];
+#pragma unroll
+    for (int pp = 0; pp < PARTS; ++pp) planes[pp] = a.Mp[T.g][pp];
+    dma_split_rows<PARTS, PLANE_M, 1>(dst, planes, (unsigned)T.i0, n, k0, 32 * wave + 16 * h);
+  };
   // FP32 W chunk: 128 fibres x 32 k; thread t takes fibre t / 4, k-quad t % 4
   const int w_x = tid >> 2, w_q = tid & 3;
   const int w_slot = w_q ^ ((w_x >> 1) & 3);
@@ -741,24 +752,24 @@ __global__ __launch_bounds__(512, 1) void k_tgemm_bf16s_wide(LowpArgs a, int n_i
   const int col = lane & 15, kq = lane >> 4;
   const int frag_off = 8 * (kq ^ ((col >> 1) & 3));
   f4 acc[FX][FI];
-  auto compute = [&](const unsigned short* cm, const unsigned short* cw) {
-    s8 mf[FI][PARTS];
+  s8 mf[FI][PARTS];
+  auto read_mf = [&](const unsigned short* cm) {
 #pragma unroll
     for (int fi = 0; fi < FI; ++fi)
 #pragma unroll
       for (int pp = 0; pp < PARTS; ++pp)
         mf[fi][pp] = *reinterpret_cast<const s8*>(cm + pp * PLANE_M +
                                                   (wi * TI + fi * 16 + col) * BK + frag_off);
+  };
+  // the products of block column fx (with the M fragments of read_mf)
+  auto compute_fx = [&](const unsigned short* cw, int fx) {
+    s8 wf[PARTS];
 #pragma unroll
-    for (int fx = 0; fx < FX; ++fx) {
-      s8 wf[PARTS];
+    for (int pp = 0; pp < PARTS; ++pp)
+      wf[pp] = *reinterpret_cast<const s8*>(cw + pp * PLANE_W +
+                                            (wx * TX + fx * 16 + col) * BK + frag_off);
 #pragma unroll
-      for (int pp = 0; pp < PARTS; ++pp)
-        wf[pp] = *reinterpret_cast<const s8*>(cw + pp * PLANE_W +
-                                              (wx * TX + fx * 16 + col) * BK + frag_off);
-#pragma unroll
-      for (int fi = 0; fi < FI; ++fi) acc[fx][fi] = split_mfma_t<PARTS>(wf, mf[fi], acc[fx][fi]);
-    }
+    for (int fi = 0; fi < FI; ++fi) acc[fx][fi] = split_mfma_t<PARTS>(wf, mf[fi], acc[fx][fi]);
   };
   auto epilogue = [&](const Tile& T) {
     const int ib = T.i0 + wi * TI;
@@ -794,18 +805,34 @@ __global__ __launch_bounds__(512, 1) void k_tgemm_bf16s_wide(LowpArgs a, int n_i
 #pragma unroll
       for (int fi = 0; fi < FI; ++fi) acc[fx][fi] = f4{0.f, 0.f, 0.f, 0.f};
     // chunk c from (cm, cw); the next chunk goes into (nm, nw)
+    // The next chunk's loads are spread over this chunk's products: issued
+    // together after the barrier, every wave's would queue behind the others'
+    // and hold back its first product.  W goes first (from HBM), the M copy
+    // in two halves after the first and second block columns, and W is split
+    // and stored before the last column.  Past the last chunk of the last
+    // tile they reload this tile's first chunk into the free buffers, so the
+    // step has no branches.
     auto step = [&](int c, const unsigned short* cm, const unsigned short* cw, unsigned short* nm,
                     unsigned short* nw) {
       const bool in_tile = c + 1 < nchunks;
-      const bool more = in_tile || next_tile;
-      if (more) {
-        const Tile& T = in_tile ? cur : nxt;
-        const int k0 = in_tile ? (c + 1) * BK : 0;
-        dma_m(nm, T, k0);
-        load_w(T, k0);
-      }
-      compute(cm, cw);
-      if (more) store_w(nw);
+      const Tile& T = (!in_tile && next_tile) ? nxt : cur;
+      const int k0 = in_tile ? (c + 1) * BK : 0;
+      load_w(T, k0);
+      read_mf(cm);
+      __builtin_amdgcn_sched_barrier(0);
+      compute_fx(cw, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      dma_m_half(nm, T, k0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      compute_fx(cw, 1);
+      __builtin_amdgcn_sched_barrier(0);
+      dma_m_half(nm, T, k0, 1);
+      __builtin_amdgcn_sched_barrier(0);
+      compute_fx(cw, 2);
+      __builtin_amdgcn_sched_barrier(0);
+      store_w(nw);
+      __builtin_amdgcn_sched_barrier(0);
+      compute_fx(cw, 3);
       __syncthreads();   // the next chunk has landed and nobody reads (cm, cw) any more
     };
     for (int c = 0; c < nchunks; c += 2) {
