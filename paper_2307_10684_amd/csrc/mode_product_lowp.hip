@@ -804,8 +804,8 @@ __global__ __launch_bounds__(512, 1) void k_tgemm_bf16s_wide(LowpArgs a, int n_i
     for (int fx = 0; fx < FX; ++fx)
 #pragma unroll
       for (int fi = 0; fi < FI; ++fi) acc[fx][fi] = f4{0.f, 0.f, 0.f, 0.f};
-    // chunk c from (cm, cw); the next chunk goes into (nm, nw)
-    // The next chunk's loads are spread over this chunk's products: issued
+    // Chunk c from (cm, cw); the next chunk goes into (nm, nw).  Its loads
+    // are spread over this chunk's products: issued
     // together after the barrier, every wave's would queue behind the others'
     // and hold back its first product.  W goes first (from HBM), the M copy
     // in two halves after the first and second block columns, and W is split
