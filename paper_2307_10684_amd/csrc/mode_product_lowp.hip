@@ -947,11 +947,13 @@ hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* co
     for (int p = 0; p < parts; ++p)
       aligned = aligned && (reinterpret_cast<uintptr_t>(Mp[g].p[p]) % 16 == 0);
   }
-  // evenly tiled by 256 rows, three parts: the wide persistent tiles, one
-  // workgroup per CU (measured at 256^3: 109 us against 116 us for the
-  // single-buffered 128 x 128 tiles below); their epilogue stores 16-byte
-  // pieces of out (and reads Y, Z so), which must then be 16-byte aligned too
-  bool wide = parts == 3 && aligned && n % 256 == 0 && X % 128 == 0;
+  // evenly tiled by 256 rows, two or three parts: the wide persistent tiles,
+  // one workgroup per CU (measured at 256^3: three parts 109 us against 116 us
+  // for the single-buffered 128 x 128 tiles below; two parts, with the loads
+  // spread over the products, 79 against 82 us, bitwise equal); their epilogue
+  // stores 16-byte pieces of out (and reads Y, Z so), which must then be
+  // 16-byte aligned too
+  bool wide = parts >= 2 && aligned && n % 256 == 0 && X % 128 == 0;
   for (int g = 0; wide && g < group; ++g)
     wide = reinterpret_cast<uintptr_t>(out[g]) % 16 == 0 &&
            !(Y && Y[g] && reinterpret_cast<uintptr_t>(Y[g]) % 16) &&
@@ -961,7 +963,14 @@ hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* co
     if (ntiles > 0x7fffffffLL) return hipErrorInvalidValue;
     const int grid = (int)std::min<long long>(ntiles, lowp_cu_count());
     const int n_itiles = n / 256, n_xtiles = (int)(X / 128);
-    if (out_f64)
+    if (parts == 2) {
+      if (out_f64)
+        hipLaunchKernelGGL((k_tgemm_bf16s_wide<2, kOutF64>), dim3(grid), dim3(512), 0, s, a,
+                           n_itiles, n_xtiles, (int)ntiles);
+      else
+        hipLaunchKernelGGL((k_tgemm_bf16s_wide<2, kOutF32>), dim3(grid), dim3(512), 0, s, a,
+                           n_itiles, n_xtiles, (int)ntiles);
+    } else if (out_f64)
       hipLaunchKernelGGL((k_tgemm_bf16s_wide<3, kOutF64>), dim3(grid), dim3(512), 0, s, a,
                          n_itiles, n_xtiles, (int)ntiles);
     else
@@ -969,9 +978,8 @@ hipError_t launch_tgemm_lowp(int precision, const void* const* W, const void* co
                          n_itiles, n_xtiles, (int)ntiles);
     return hipGetLastError();
   }
-  // evenly tiled by 128 with enough tiles: 128 x 128 tiles with one LDS buffer,
-  // two workgroups per CU (two parts at 256^3: 84.6 us against 91.1 us for the
-  // wide tiles)
+  // evenly tiled by 128 (n not a multiple of 256) with enough tiles: 128 x 128
+  // tiles with one LDS buffer, two workgroups per CU
   if (aligned && n % 128 == 0 && X % 128 == 0 && !rows64) {
     if (parts == 3)
       return out_f64 ? launch_tiles(k_tgemm_bf16s<128, 128, true, true, 3, 1>, a, 128, 128, s)
