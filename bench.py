@@ -592,7 +592,14 @@ def main(argv=None):
         bytes_per_launch = None
     elif args.precision == "f64":
         achieved = flops_per_launch / (mode_avg_ms * 1e-3) / 1e12
-        bytes_per_launch = 2 * 2 * 8 * N  # read + write one tensor per component
+        # read W and write the result for each component (32 B per point), and
+        # for the last product of each Tucker operator also the addend (C_n,
+        # C_{n2}: 16 B more), averaged over the step's plain launches; the
+        # launch that carries stage 2 is counted apart
+        plain_per_step = n_mode / max(args.steps, 1)
+        fused_per_step = n_fused / max(args.steps, 1)
+        bytes_per_launch = 2 * 2 * 8 * N + (2 * 8 * N * (2 - fused_per_step) / plain_per_step
+                                            if plain_per_step > 0 else 0.0)
         roof = {"kernel": "mode_product_f64", "bound": "mfma", "achieved": achieved,
                 "peak": PEAKS["f64_mfma_tflops"], "unit": "TFLOP/s",
                 "frac": achieved / PEAKS["f64_mfma_tflops"],
@@ -605,7 +612,17 @@ def main(argv=None):
     if n_mode:
         roof["tflops"] = flops_per_launch / (mode_avg_ms * 1e-3) / 1e12
         roof["traffic"] = _traffic_from_profiles(args.precision, w.name)
-    fused_bytes = None if bytes_per_launch is None else bytes_per_launch + 32 * N
+    # the launch that carries stage 2 (FP64): U tiles read W and U_n and write
+    # U_{n2}; V tiles read W, V_n, U_{n2} and U_n and write V_{n2}, R_u and R_v
+    # (80 B per point); the reduced-precision last product reads W (FP32), the
+    # FP64 state and the FP32 first increment and writes the FP64 state
+    # (48 B per point, 32 more than a plain FP32 launch)
+    if bytes_per_launch is None:
+        fused_bytes = None
+    elif args.precision == "f64":
+        fused_bytes = 80 * N
+    else:
+        fused_bytes = bytes_per_launch + 32 * N
     roof["fused_launch"] = None if fused_avg_ms is None else {
         "what": ("last product of the phi_1 operator, stage 2 in its epilogue"
                  if args.precision == "f64" else
