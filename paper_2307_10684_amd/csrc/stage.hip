@@ -2,6 +2,8 @@
 // eq. (7)): reaction terms G^u, G^v, the Kronecker-sum action K C as a stencil
 // when A_mu is tridiagonal, and the combinations that feed the Tucker operators.
 // All are HBM-bound streaming kernels; the state U, V is FP64 throughout.
+#include <algorithm>
+
 #include "common.h"
 #include "reaction.h"
 
@@ -35,7 +37,8 @@ __device__ __forceinline__ void xcd_block(int& bx, int& by, int& bz) {
 }
 
 // Stage 1 on LDS tiles.  A block of 64 x 4 threads owns a tile of kTX = 64
-// values of i_1 by kTY = 16 rows of i_2 and marches through ZB planes of i_3.
+// values of i_1 by kTY = 16 rows of i_2 and marches through planes z0..z1-1 of
+// i_3 (at most ZB of them).
 // The plane being computed sits in LDS with a one-point halo in i_1 and i_2
 // (zero outside the grid, where the band coefficient is zero too); two LDS
 // buffers let the next plane be written while this one is read, with one
@@ -45,17 +48,17 @@ __device__ __forceinline__ void xcd_block(int& bx, int& by, int& bz) {
 // the memory latency of the loads for a later one.  Every value of the tile is
 // read from HBM once per plane; halos come from neighbouring tiles (L2).
 constexpr int kTX = 64, kTY = 16, kRows = kTY / 4;
-constexpr int kZB = 8;   // planes per block of the tiled kernel
+constexpr int kZB = 8;      // planes per block of the tiled kernel in grouped launches
+constexpr int kZBmax = 32;  // most planes one block marches in single-problem launches
 
 template <typename TR, int ZB>
 __device__ __forceinline__ void etd_stage1_tile(const StageGeom& g, const Reaction& r,
                                                 const double* __restrict__ U,
                                                 const double* __restrict__ V, void* Ru, void* Rv,
-                                                int bx, int by, int bz) {
+                                                int bx, int by, int z0, int z1) {
   const int n1 = g.n[0], n2 = g.d >= 2 ? g.n[1] : 1, n3 = g.d >= 3 ? g.n[2] : 1;
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 64 + tx;
   const int x0 = bx * kTX, y0 = by * kTY;
-  const int z0 = bz * ZB, z1 = min(z0 + ZB, n3);
   const unsigned P = (unsigned)n1 * (unsigned)n2;
 
   __shared__ double sU[2][kTY + 2][kTX + 2];   // double-buffered planes
@@ -284,7 +287,12 @@ __global__ __launch_bounds__(256) void k_etd_stage1_tile(StageGeom g, Reaction r
                                                          void* Rv) {
   int bx, by, bz;
   xcd_block(bx, by, bz);
-  etd_stage1_tile<TR, ZB>(g, r, U, V, Ru, Rv, bx, by, bz);
+  // block bz marches planes [bz n3 / gz, (bz + 1) n3 / gz): every block gets
+  // floor or ceil of n3 / gz planes (the launcher keeps that at most ZB)
+  const int n3 = g.d >= 3 ? g.n[2] : 1;
+  const int z0 = (int)((long long)bz * n3 / gridDim.z);
+  const int z1 = (int)((long long)(bz + 1) * n3 / gridDim.z);
+  etd_stage1_tile<TR, ZB>(g, r, U, V, Ru, Rv, bx, by, z0, z1);
 }
 
 // Grouped stage 1 over several problems of one kernel variant (KIND): job j
@@ -305,9 +313,11 @@ __global__ __launch_bounds__(256) void k_etd_stage1_grouped(const StageJob* __re
   const StageJob& j = jobs[lo];
   const int local = (int)(b - j.block_begin);
   const int bx = local % j.gx, rest = local / j.gx;
-  if (KIND == kStage1Tile)
-    etd_stage1_tile<TR, kZB>(j.g, j.r, j.U, j.V, j.R[0], j.R[1], bx, rest % j.gy, rest / j.gy);
-  else
+  if (KIND == kStage1Tile) {
+    const int z0 = (rest / j.gy) * kZB, n3 = j.g.d >= 3 ? j.g.n[2] : 1;
+    etd_stage1_tile<TR, kZB>(j.g, j.r, j.U, j.V, j.R[0], j.R[1], bx, rest % j.gy, z0,
+                             min(z0 + kZB, n3));
+  } else
     etd_stage1_point<TR>(j.g, j.r, j.U, j.V, j.R[0], j.R[1], bx, rest % j.gy, rest / j.gy);
 }
 
@@ -468,33 +478,54 @@ int stage1_plan(const StageGeom& g, int& kind, int& gx, int& gy, int& gz) {
                                                                                : kStage1Point;
   gx = (g.n[0] + 63) / 64;
   gy = kind == kStage1Tile ? (n2 + kTY - 1) / kTY : (n2 + 3) / 4;
+  // tile kernel: kZB planes per block, the layout of grouped launches
+  // (launch_etd_stage1 re-splits the planes of a single problem)
   gz = kind == kStage1Tile ? (n3 + kZB - 1) / kZB : n3;
   return gx * gy * gz;
+}
+
+// Resident workgroups per CU of a tile-kernel variant (cached; 3 if the query fails).
+template <typename TR>
+static int stage1_tile_occupancy() {
+  static int occ = 0;
+  if (occ == 0 &&
+      (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+           &occ, reinterpret_cast<const void*>(&k_etd_stage1_tile<TR, kZBmax>), 256, 0) !=
+           hipSuccess ||
+       occ <= 0))
+    occ = 3;
+  return occ;
 }
 
 hipError_t launch_etd_stage1(const StageGeom& g, const Reaction& r, const double* U,
                              const double* V, void* Ru, void* Rv, int r_f32, hipStream_t s) {
   int kind, gx, gy, gz;
   stage1_plan(g, kind, gx, gy, gz);
-  // Tiles that march 4 planes instead of kZB where kZB-plane blocks would give
-  // a CU fewer than four (the same values; measured, FP64: 128^3 21.7 against
-  // 25.5 us; 256^3, 2048 blocks, keeps kZB: 131-134 against 140 us with 4)
-  const bool short_march =
-      kind == kStage1Tile && (long long)gx * gy * gz < 4LL * stage_cu_count();
-  if (short_march) gz = (g.n[2] + 3) / 4;
+  if (kind == kStage1Tile) {
+    // One round of resident workgroups: the planes are split evenly over
+    // gz = (workgroups the chip holds at once) / (tiles per plane) blocks per
+    // column of tiles, at most kZBmax planes each.  A grid of several rounds
+    // leaves part of the chip idle in its last one and pays a three-plane
+    // start-up per block more often (measured, FP64, same values: 256^3 121 against
+    // 134 us with 8-plane blocks, 128^3 20.7 against 22.0, 200x150x101 27.7
+    // against 33.0).
+    const int n3 = g.d >= 3 ? g.n[2] : 1;
+    const long long slots =
+        (long long)(r_f32 ? stage1_tile_occupancy<float>() : stage1_tile_occupancy<double>()) *
+        stage_cu_count();
+    long long z = slots / ((long long)gx * gy);
+    z = std::max<long long>(z, (n3 + kZBmax - 1) / kZBmax);
+    gz = (int)std::min<long long>(std::max<long long>(z, 1), n3);
+  }
   if (gy > 65535 || gz > 65535) return hipErrorInvalidValue;
   const dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)gz), block(64, 4);
   if (kind == kStage1Tile) {
-    if (short_march) {
-      if (r_f32)
-        hipLaunchKernelGGL((k_etd_stage1_tile<float, 4>), grid, block, 0, s, g, r, U, V, Ru, Rv);
-      else
-        hipLaunchKernelGGL((k_etd_stage1_tile<double, 4>), grid, block, 0, s, g, r, U, V, Ru, Rv);
-    } else if (r_f32) {
-      hipLaunchKernelGGL((k_etd_stage1_tile<float, kZB>), grid, block, 0, s, g, r, U, V, Ru, Rv);
-    } else {
-      hipLaunchKernelGGL((k_etd_stage1_tile<double, kZB>), grid, block, 0, s, g, r, U, V, Ru, Rv);
-    }
+    if (r_f32)
+      hipLaunchKernelGGL((k_etd_stage1_tile<float, kZBmax>), grid, block, 0, s, g, r, U, V, Ru,
+                         Rv);
+    else
+      hipLaunchKernelGGL((k_etd_stage1_tile<double, kZBmax>), grid, block, 0, s, g, r, U, V, Ru,
+                         Rv);
   } else {
     if (r_f32)
       hipLaunchKernelGGL(k_etd_stage1_point<float>, grid, block, 0, s, g, r, U, V, Ru, Rv);
