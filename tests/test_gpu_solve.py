@@ -83,9 +83,12 @@ CASES = [
     ("fhn3d_128x128x40_10", S.with_shape(S.fhn_3d(), (128, 128, 40)), 10),
     ("bruss3d_64x64x96_10", S.with_shape(S.brusselator_3d(), (64, 64, 96)), 10),
     ("schnakenberg2d_128x128_20", S.with_shape(S.schnakenberg_2d(), (128, 128)), 20),
-    # 3D grids of 2^20 points or more with n1 = 64 or 256: stage 1 by whole-row waves
+    # 3D grids of 2^20 points or more: stage 1 on LDS tiles, the planes split
+    # over as many blocks per tile column as the chip holds at once (1-2 planes
+    # each here, uneven); the last case has partial tiles in i1 and i2 as well
     ("fhn3d_64x128x128_5", S.with_shape(S.fhn_3d(), (64, 128, 128)), 5),
     ("bruss3d_256x64x72_3", S.with_shape(S.brusselator_3d(), (256, 64, 72)), 3),
+    ("bruss3d_100x90x120_3", S.with_shape(S.brusselator_3d(), (100, 90, 120)), 3),
     # 2D grids of 64 x n2 (n2 <= 64): every step in one cooperative launch, four
     # columns per workgroup; a last workgroup with fewer columns (30, 3), the
     # advective Brusselator (non-symmetric bands) and the DIB model
