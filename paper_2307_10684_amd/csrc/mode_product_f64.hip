@@ -903,7 +903,7 @@ __global__ __launch_bounds__(64 * WI * WX, MINB) void k_mode_f64_persist(ModeArg
             store(out + o, val);
           }
     };
-    // Outputs larger than the last-level cache can hold go out with streaming
+    // Large outputs (stream_out, set by the launcher) go out with streaming
     // (non-temporal) stores; the U tiles of a stage-2 launch keep ordinary ones,
     // since their V tiles read U_{n2} straight back.
     if (!S2 && stream_out)
