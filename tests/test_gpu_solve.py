@@ -89,6 +89,8 @@ CASES = [
     ("fhn3d_64x128x128_5", S.with_shape(S.fhn_3d(), (64, 128, 128)), 5),
     ("bruss3d_256x64x72_3", S.with_shape(S.brusselator_3d(), (256, 64, 72)), 3),
     ("bruss3d_100x90x120_3", S.with_shape(S.brusselator_3d(), (100, 90, 120)), 3),
+    # thin 3D grid: 256 tiles per plane, so 4 planes over 3 blocks per tile column
+    ("fhn3d_512x512x4_2", S.with_shape(S.fhn_3d(), (512, 512, 4)), 2),
     # 2D grids of 64 x n2 (n2 <= 64): every step in one cooperative launch, four
     # columns per workgroup; a last workgroup with fewer columns (30, 3), the
     # advective Brusselator (non-symmetric bands) and the DIB model
